@@ -1,0 +1,227 @@
+/*
+ * epic.h -- C ABI of the MI355X EPIC/MOFF imaging hot path.
+ *
+ * The library turns a channelised stream of 4+4-bit complex antenna voltages
+ * into accumulated polarisation image cubes, following the MOFF/EPIC imaging
+ * chain of Krishnan et al. (MNRAS 2023), Sec. 2 (Eq. 4) and Sec. 3:
+ *
+ *   unpack each 4+4-bit sample                         (Sec. 2.1)
+ *   -> grid every antenna through its gridding kernel  (Eq. 4, Sec. 3.1)
+ *   -> spatial 2D inverse Fourier transform            (Eq. 4, Sec. 2.2)
+ *   -> square / cross-multiply the polarisations       (Eq. 5, Sec. 3.2)
+ *   -> accumulate over the integration                 (Eq. 4 time average, Sec. 2.2)
+ *
+ * Conventions shared by every entry point:
+ *   - All functions return an epic_status and never abort, throw or exit.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the plan's device (e.g. torch tensors' data_ptr()).
+ *   - A hip_stream argument is a hipStream_t passed as void*; NULL means the
+ *     null stream of the plan's device.  Only epic_plan and epic_destroy
+ *     synchronise; every other call only enqueues work on the given stream.
+ *   - A plan is not thread-safe: use one plan from one host thread at a time.
+ *   - Validation happens before any side effect: a call that returns
+ *     EPIC_E_ARG / EPIC_E_GEOMETRY / EPIC_E_STATE has changed nothing.
+ *   - A device fault reported by the HIP runtime is returned as EPIC_E_DEVICE
+ *     and is sticky: the plan refuses further work until destroyed.
+ */
+#ifndef EPIC_H
+#define EPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPIC_ABI_VERSION 1
+
+typedef struct epic_plan_s* epic_plan_t;   /* opaque, owned by the library */
+
+typedef enum {
+    EPIC_OK = 0,
+    EPIC_E_ARG = 1,          /* bad pointer, size, enum or combination */
+    EPIC_E_GEOMETRY = 2,     /* an antenna footprint falls outside the grid */
+    EPIC_E_NOMEM = 3,        /* device or host allocation failed / size overflow */
+    EPIC_E_DEVICE = 4,       /* HIP runtime or kernel error (sticky) */
+    EPIC_E_UNSUPPORTED = 5,  /* valid request this build does not implement */
+    EPIC_E_STATE = 6         /* call not allowed in the plan's current state */
+} epic_status;
+
+/* Arithmetic of the grid / transform stages.  Accumulation is always FP32. */
+typedef enum {
+    EPIC_FP32 = 0,   /* FP32 vector ALU: gather gridding + register FFT */
+    EPIC_FP16 = 1,   /* FP16 matrix cores (MFMA) for the transform stages */
+    EPIC_FP8 = 2     /* FP8 e4m3 matrix cores for gridding, FP16 transforms */
+} epic_precision;
+
+/* How the gridding step (Eq. 4, W_a * E_a summed over antennas) runs. */
+typedef enum {
+    EPIC_GRID_AUTO = 0,        /* library / autotuner choice */
+    EPIC_GRID_GATHER = 1,      /* each aperture cell sums its antenna list (FP32 ALU) */
+    EPIC_GRID_DENSE_GEMM = 2,  /* kernel matrix x E-field GEMM on matrix cores */
+    EPIC_GRID_BLOCK_GEMM = 3   /* reserved: block-sparse GEMM */
+} epic_gridder;
+
+/* Output products per pixel. */
+typedef enum {
+    EPIC_OUT_POL = 0,     /* dual pol: XX*, YY*, Re XY*, Im XY*; single pol: XX* */
+    EPIC_OUT_STOKES = 1   /* dual pol only: I, Q, U, V (linear feeds) */
+} epic_output;
+
+enum {
+    EPIC_F_GRAPH = 1u,            /* replay accumulate steps from a captured hipGraph */
+    EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time */
+    EPIC_F_DRY_RUN = 4u,          /* validate and size on the CPU; touch no device */
+    EPIC_F_REMOVE_AUTOCORR = 8u   /* subtract each antenna's own power term (a = b) */
+};
+
+/*
+ * One antenna array (or band) to image.  Sec. 2.1 describes the station this
+ * is shaped after: dual-polarised dipoles, 25 kHz channels, 4+4-bit samples.
+ *
+ * Geometry (Sec. 3.1: antennas are mapped to their nearest grid cell): for
+ * channel c the centre frequency is f_c = freq0_hz + c * dfreq_hz; antenna a
+ * at (x, y) metres has fractional cell coordinate
+ *     g = (x * f_c / 299792458) / grid_dl + grid_n / 2      (same for y),
+ * evaluated in FP64 in exactly this order without fused multiply-add, and its
+ * nearest cell is floor(g + 0.5).  Its kernel covers the kernel_k x kernel_k
+ * cells centred there; all of them must lie in [0, grid_n - 1] at every
+ * channel, else epic_plan returns EPIC_E_GEOMETRY.  Image pixel (i, j) looks
+ * at direction cosines l = (i - N/2) / (N grid_dl), m = (j - N/2) / (N grid_dl).
+ */
+typedef struct {
+    int32_t n_ant;               /* A >= 1, A * n_pol <= 65536 */
+    int32_t n_pol;               /* P: 1 or 2 (X, Y) */
+    int32_t n_chan;              /* C >= 1 */
+    int32_t grid_n;              /* N: multiple of 16 in [16, 128] */
+    int32_t kernel_k;            /* K: odd, 1..7 */
+    int32_t nibble_order;        /* 0: real part in the high nibble; 1: swapped */
+    double grid_dl;              /* grid spacing in wavelengths (> 0) */
+    double freq0_hz;             /* centre frequency of channel 0 (> 0) */
+    double dfreq_hz;             /* channel spacing (>= 0) */
+    const double* ant_xy_m;      /* host [A][2] east, north in metres; copied */
+    const float* taps;           /* host [C][A][P][K][K][2] complex kernel taps
+                                    (row-major [dy][dx], re/im), or NULL for the
+                                    default Gaussian; copied */
+    double kernel_sigma_cells;   /* Gaussian sigma in cells when taps == NULL
+                                    (<= 0 selects 0.5).  The Gaussian weighs tap
+                                    (dx, dy) by exp(-d^2 / (2 sigma^2)), d the
+                                    distance from the tap's cell centre to g,
+                                    normalised to unit sum. */
+} epic_array_desc;
+
+typedef struct {
+    int32_t n_sub;                 /* number of arrays / bands, 1..16 */
+    const epic_array_desc* sub;    /* host [n_sub]; copied */
+    int32_t precision;             /* epic_precision */
+    int32_t gridder;               /* epic_gridder */
+    int32_t output;                /* epic_output */
+    int32_t device;                /* HIP device ordinal */
+    int64_t max_time;              /* largest n_time a single accumulate call may pass (>= 1) */
+    uint32_t flags;                /* EPIC_F_* */
+    int32_t reserved[4];           /* must be zero */
+} epic_plan_desc;
+
+/* Plan facts for callers and tests (all sizes in bytes). */
+typedef struct {
+    int32_t n_sub;
+    int32_t precision, gridder, output;
+    int32_t npp[16];               /* products per pixel per sub-array (1 or 4) */
+    int32_t slots[16];             /* time slots (partial accumulators) per sub-array */
+    int32_t window_max[16];        /* largest aperture window side over channels */
+    int32_t threads[16];           /* workgroup size of the sub-array's kernel */
+    int64_t device_bytes;          /* device memory owned by the plan */
+    int64_t lds_bytes[16];         /* LDS per workgroup of each sub-array's kernel */
+    int32_t graph;                 /* 1 if accumulate replays a hipGraph */
+    int32_t autotuned;             /* 1 if launch shapes came from timing */
+} epic_plan_info;
+
+/*
+ * epic_plan -- validate the arrays, compute the geometry (Sec. 3.1 nearest-cell
+ * mapping) in FP64 on the host, compute the kernel taps and transform tables
+ * in FP64 on the device, and allocate the accumulators.
+ *   desc        host, read during the call only.
+ *   hip_stream  stream for the one-off device set-up (synchronised before return).
+ *   out         host; receives the new plan on EPIC_OK, NULL otherwise.
+ * Errors: EPIC_E_ARG (bad field, non-zero reserved), EPIC_E_GEOMETRY,
+ * EPIC_E_NOMEM, EPIC_E_DEVICE, EPIC_E_UNSUPPORTED (e.g. a grid size with no
+ * kernel).  With EPIC_F_DRY_RUN no HIP call is made; the plan can be queried
+ * and destroyed but accumulate / readout return EPIC_E_STATE.
+ * The accumulators start at zero.
+ */
+epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t* out);
+
+/*
+ * epic_grid_fft_accumulate -- the hot path.  For every sub-array, channel and
+ * time sample: unpack, grid (Eq. 4), 2D transform (Eq. 4), form the
+ * polarisation products (Eq. 5) and add them into the plan's FP32 accumulators
+ * (the time sum of Eq. 4; no 1/T normalisation).
+ *   d_samples   host array [n_sub] of device pointers; sub-array s points at
+ *               uint8 [n_time][C_s][A_s][P_s] bytes, one 4+4-bit complex
+ *               sample each (two's complement nibbles).  Read only; must stay
+ *               valid until the stream passes this call.
+ *   n_time      0..max_time spectra (0 is a no-op).
+ * Errors: EPIC_E_ARG (NULL pointer, n_time out of range), EPIC_E_STATE (dry
+ * run or sticky error), EPIC_E_DEVICE (launch failure).
+ */
+epic_status epic_grid_fft_accumulate(epic_plan_t plan, const uint8_t* const* d_samples,
+                                     int64_t n_time, void* hip_stream);
+
+/*
+ * epic_readout -- reduce the plan's partial accumulators in a fixed order into
+ * the caller's image cubes, then optionally zero them (start a new integration).
+ *   d_images    host array [n_sub] of device pointers; sub-array s receives
+ *               float [C_s][NPP_s][N_s][N_s], indexed [c][product][j][i]
+ *               (j: m axis, i: l axis).  Products: EPIC_OUT_POL dual pol
+ *               XX*, YY*, Re XY*, Im XY*; single pol XX*; EPIC_OUT_STOKES
+ *               I = XX*+YY*, Q = XX*-YY*, U = 2 Re XY*, V = -2 Im XY*.
+ *               Overwritten; must stay valid until the stream passes the call.
+ *   reset       non-zero: zero the accumulators after reading.
+ * Errors: EPIC_E_ARG, EPIC_E_STATE, EPIC_E_DEVICE.
+ */
+epic_status epic_readout(epic_plan_t plan, float* const* d_images, int32_t reset, void* hip_stream);
+
+/*
+ * epic_set_gains -- per-antenna complex gains (delay / phase / amplitude
+ * corrections, Sec. 2.2's delay correction step) folded into the kernel taps
+ * of one sub-array: tap'(c, a, p) = g(c, a, p) * tap(c, a, p).  Replaces any
+ * previous gains (NULL restores unit gains).  Enqueued on hip_stream; later
+ * accumulate calls on the same stream see the new taps.
+ *   h_gains     host float [C][A][P][2] (re, im); copied before return.
+ * Errors: EPIC_E_ARG, EPIC_E_STATE, EPIC_E_DEVICE.
+ */
+epic_status epic_set_gains(epic_plan_t plan, int32_t sub, const float* h_gains, void* hip_stream);
+
+/* epic_plan_query -- fill *info (host).  Works on dry-run plans.  EPIC_E_ARG on NULL. */
+epic_status epic_plan_query(epic_plan_t plan, epic_plan_info* info);
+
+/*
+ * epic_debug_geometry -- copy the plan's nearest-cell indices of sub-array
+ * `sub` to host int32 [C][A][2] (x, y) for bit-exact comparison.  Works on
+ * dry-run plans.  EPIC_E_ARG on bad arguments.
+ */
+epic_status epic_debug_geometry(epic_plan_t plan, int32_t sub, int32_t* h_cells);
+
+/*
+ * epic_debug_unpack -- run the device 4+4-bit decoder of the hot path on n
+ * bytes: d_out (device float [n][2]) receives (re, im).  Enqueued on
+ * hip_stream.  EPIC_E_ARG on NULL pointers or n < 0; EPIC_E_DEVICE on launch
+ * failure.
+ */
+epic_status epic_debug_unpack(const uint8_t* d_bytes, int64_t n, int32_t nibble_order,
+                              float* d_out, void* hip_stream);
+
+/* epic_destroy -- synchronise the plan's device, free everything.  NULL is a no-op. */
+epic_status epic_destroy(epic_plan_t plan);
+
+/* epic_status_str -- static, NUL-terminated name of a status code. */
+const char* epic_status_str(epic_status status);
+
+/* epic_abi_version -- EPIC_ABI_VERSION of the built library. */
+int32_t epic_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPIC_H */

@@ -1,0 +1,447 @@
+// Host side of the EPIC/MOFF library: argument validation, FP64 geometry,
+// gather lists, device allocation and the extern "C" entry points of
+// include/epic.h.  Built with -ffp-contract=off: the nearest-cell indices must
+// be bit-identical to an FP64 evaluation of the documented formula.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "epic_internal.hpp"
+
+using namespace epic;
+
+namespace {
+
+constexpr double kC0 = 299792458.0;   // m/s
+constexpr uint32_t kMagic = 0x45504943u;  // 'EPIC'
+constexpr uint32_t kKnownFlags = EPIC_F_GRAPH | EPIC_F_AUTOTUNE | EPIC_F_DRY_RUN | EPIC_F_REMOVE_AUTOCORR;
+
+struct SubHost {
+    epic_array_desc desc{};
+    std::vector<double> ant_xy;      // [A][2]
+    std::vector<float> user_taps;    // [C][A][P][K][K][2] or empty
+    std::vector<int32_t> cells;      // [C][A][2]
+    std::vector<double> gfrac;       // [C][A][2]
+    std::vector<ChanInfo> chans;     // [C]
+    std::vector<uint32_t> cell_ptr;  // concatenated per channel
+    std::vector<uint16_t> ent_ant;
+    std::vector<uint8_t> ent_tap;
+    SubDev dev{};
+};
+
+}  // namespace
+
+struct epic_plan_s {
+    uint32_t magic = kMagic;
+    epic_plan_desc desc{};
+    std::vector<SubHost> subs;
+    int dry_run = 0;
+    int device = 0;
+    int num_cu = 256;
+    epic_status sticky = EPIC_OK;
+    std::vector<void*> allocations;
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+epic_status validate_sub(const epic_array_desc& s) {
+    if (s.n_ant < 1 || (s.n_pol != 1 && s.n_pol != 2) || s.n_chan < 1) return EPIC_E_ARG;
+    if ((int64_t)s.n_ant * s.n_pol > 65536) return EPIC_E_ARG;
+    if (s.grid_n < 16 || s.grid_n > kMaxGridN || (s.grid_n % 16) != 0) return EPIC_E_ARG;
+    if (s.kernel_k < 1 || s.kernel_k > 7 || (s.kernel_k & 1) == 0) return EPIC_E_ARG;
+    if (s.nibble_order != 0 && s.nibble_order != 1) return EPIC_E_ARG;
+    if (!finite(s.grid_dl) || !(s.grid_dl > 0.0)) return EPIC_E_ARG;
+    if (!finite(s.freq0_hz) || !(s.freq0_hz > 0.0)) return EPIC_E_ARG;
+    if (!finite(s.dfreq_hz) || s.dfreq_hz < 0.0) return EPIC_E_ARG;
+    if (!s.ant_xy_m) return EPIC_E_ARG;
+    if (!finite(s.kernel_sigma_cells)) return EPIC_E_ARG;
+    for (int64_t k = 0; k < 2LL * s.n_ant; ++k)
+        if (!finite(s.ant_xy_m[k])) return EPIC_E_ARG;
+    if (s.taps) {
+        int64_t n = (int64_t)s.n_chan * s.n_ant * s.n_pol * s.kernel_k * s.kernel_k * 2;
+        for (int64_t k = 0; k < n; ++k)
+            if (!std::isfinite(s.taps[k])) return EPIC_E_ARG;
+    }
+    // entry counts must fit the 32-bit tables
+    if ((int64_t)s.n_chan * s.n_ant * s.kernel_k * s.kernel_k > (int64_t)std::numeric_limits<int32_t>::max())
+        return EPIC_E_NOMEM;
+    return EPIC_OK;
+}
+
+// Nearest-cell geometry, Sec. 3.1.  The operation order is part of the ABI.
+epic_status geometry(SubHost& h) {
+    const epic_array_desc& s = h.desc;
+    const int A = s.n_ant, C = s.n_chan, N = s.grid_n, hk = s.kernel_k / 2;
+    h.cells.assign((size_t)C * A * 2, 0);
+    h.gfrac.assign((size_t)C * A * 2, 0.0);
+    for (int c = 0; c < C; ++c) {
+        double f = s.freq0_hz + (double)c * s.dfreq_hz;
+        for (int a = 0; a < A; ++a)
+            for (int ax = 0; ax < 2; ++ax) {
+                double u = h.ant_xy[2 * a + ax] * f / kC0;
+                double g = u / s.grid_dl + 0.5 * (double)N;
+                double p = std::floor(g + 0.5);
+                if (!(p - hk >= 0.0) || !(p + hk <= (double)(N - 1))) return EPIC_E_GEOMETRY;
+                size_t o = ((size_t)c * A + a) * 2 + ax;
+                h.gfrac[o] = g;
+                h.cells[o] = (int32_t)p;
+            }
+    }
+    return EPIC_OK;
+}
+
+// Per-channel aperture window and gather lists: for every window cell, the
+// (antenna, tap) pairs whose kernel footprint covers it, in antenna order.
+void build_gather(SubHost& h) {
+    const epic_array_desc& s = h.desc;
+    const int A = s.n_ant, C = s.n_chan, K = s.kernel_k, hk = K / 2;
+    h.chans.assign(C, ChanInfo{});
+    h.cell_ptr.clear();
+    h.ent_ant.clear();
+    h.ent_tap.clear();
+    int Rmax = 0, Wmax = 0, Emax = 0;
+    std::vector<uint32_t> count;
+    for (int c = 0; c < C; ++c) {
+        const int32_t* cc = &h.cells[(size_t)c * A * 2];
+        int x0 = cc[0], x1 = cc[0], y0 = cc[1], y1 = cc[1];
+        for (int a = 1; a < A; ++a) {
+            x0 = std::min(x0, cc[2 * a]); x1 = std::max(x1, cc[2 * a]);
+            y0 = std::min(y0, cc[2 * a + 1]); y1 = std::max(y1, cc[2 * a + 1]);
+        }
+        x0 -= hk; y0 -= hk; x1 += hk; y1 += hk;
+        const int W = x1 - x0 + 1, R = y1 - y0 + 1, cellsN = R * W;
+        ChanInfo ci{};
+        ci.x0 = x0; ci.y0 = y0; ci.R = R; ci.W = W;
+        ci.cell_off = (int32_t)h.cell_ptr.size();
+        ci.ent_off = (int32_t)h.ent_ant.size();
+        ci.n_ent = A * K * K;
+        count.assign((size_t)cellsN + 1, 0u);
+        for (int a = 0; a < A; ++a)
+            for (int dy = -hk; dy <= hk; ++dy)
+                for (int dx = -hk; dx <= hk; ++dx) {
+                    int w = cc[2 * a] + dx - x0, r = cc[2 * a + 1] + dy - y0;
+                    count[(size_t)r * W + w + 1]++;
+                }
+        for (int k = 0; k < cellsN; ++k) count[k + 1] += count[k];
+        h.cell_ptr.insert(h.cell_ptr.end(), count.begin(), count.end());
+        std::vector<uint32_t> fill(count.begin(), count.end() - 1);
+        h.ent_ant.resize((size_t)ci.ent_off + ci.n_ent);
+        h.ent_tap.resize((size_t)ci.ent_off + ci.n_ent);
+        for (int a = 0; a < A; ++a)
+            for (int dy = -hk; dy <= hk; ++dy)
+                for (int dx = -hk; dx <= hk; ++dx) {
+                    int w = cc[2 * a] + dx - x0, r = cc[2 * a + 1] + dy - y0;
+                    uint32_t e = fill[(size_t)r * W + w]++;
+                    h.ent_ant[(size_t)ci.ent_off + e] = (uint16_t)a;
+                    h.ent_tap[(size_t)ci.ent_off + e] = (uint8_t)((dy + hk) * K + (dx + hk));
+                }
+        h.chans[c] = ci;
+        Rmax = std::max(Rmax, R); Wmax = std::max(Wmax, W); Emax = std::max(Emax, ci.n_ent);
+    }
+    h.dev.Rmax = Rmax; h.dev.Wmax = Wmax; h.dev.Emax = Emax;
+}
+
+epic_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return EPIC_OK;
+    if (e == hipErrorOutOfMemory) return EPIC_E_NOMEM;
+    return EPIC_E_DEVICE;
+}
+
+template <typename T>
+epic_status dalloc(epic_plan_s* p, T** ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) return EPIC_OK;
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, count * sizeof(T));
+    if (e != hipSuccess) return hip_status(e);
+    p->allocations.push_back(v);
+    p->device_bytes += (int64_t)(count * sizeof(T));
+    *ptr = static_cast<T*>(v);
+    return EPIC_OK;
+}
+
+template <typename T>
+epic_status upload(epic_plan_s* p, T** ptr, const std::vector<T>& v, hipStream_t st) {
+    epic_status s = dalloc(p, ptr, v.size());
+    if (s != EPIC_OK || v.empty()) return s;
+    return hip_status(hipMemcpyAsync(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+void free_all(epic_plan_s* p) {
+    if (!p->dry_run) {
+        hipSetDevice(p->device);
+        hipDeviceSynchronize();
+        for (void* v : p->allocations) hipFree(v);
+    }
+    p->allocations.clear();
+}
+
+// Time slots: enough independent (channel, slot) workgroups to fill the chip
+// a few times over, never more slots than spectra per call.
+int choose_slots(const SubDev& d, int num_cu, int64_t max_time, int n_sub) {
+    const int64_t target = 4LL * num_cu / std::max(1, n_sub) + 1;
+    int64_t per = (int64_t)d.C * d.KS;
+    int64_t S = (target + per - 1) / per;
+    S = std::max<int64_t>(1, std::min<int64_t>(S, 64));
+    S = std::min<int64_t>(S, max_time);
+    return (int)S;
+}
+
+epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p) {
+    p->desc = *desc;
+    p->desc.sub = nullptr;
+    p->dry_run = (desc->flags & EPIC_F_DRY_RUN) ? 1 : 0;
+    p->device = desc->device;
+    p->subs.resize(desc->n_sub);
+    for (int k = 0; k < desc->n_sub; ++k) {
+        SubHost& h = p->subs[k];
+        h.desc = desc->sub[k];
+        h.ant_xy.assign(desc->sub[k].ant_xy_m, desc->sub[k].ant_xy_m + 2 * (size_t)h.desc.n_ant);
+        h.desc.ant_xy_m = nullptr;
+        if (desc->sub[k].taps) {
+            size_t n = (size_t)h.desc.n_chan * h.desc.n_ant * h.desc.n_pol * h.desc.kernel_k * h.desc.kernel_k * 2;
+            h.user_taps.assign(desc->sub[k].taps, desc->sub[k].taps + n);
+        }
+        h.desc.taps = nullptr;
+        epic_status s = geometry(h);
+        if (s != EPIC_OK) return s;
+        build_gather(h);
+        SubDev& d = h.dev;
+        d.A = h.desc.n_ant; d.P = h.desc.n_pol; d.C = h.desc.n_chan; d.N = h.desc.grid_n;
+        d.K = h.desc.kernel_k; d.NPP = (d.P == 2) ? 4 : 1; d.nibble_order = h.desc.nibble_order;
+    }
+    if (!p->dry_run) {
+        hipError_t e = hipSetDevice(p->device);
+        if (e != hipSuccess) return EPIC_E_ARG;
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cu > 0)
+            p->num_cu = cu;
+    }
+    for (SubHost& h : p->subs) {
+        SubDev& d = h.dev;
+        hipError_t e = fp32_configure(d, p->dry_run ? -1 : p->device);
+        if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
+        if (e != hipSuccess) return hip_status(e);
+        d.S = choose_slots(d, p->num_cu, desc->max_time, desc->n_sub);
+        // size checks (also in dry run)
+        const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
+        if (slot_bytes > 64.0 * (1ull << 30)) return EPIC_E_NOMEM;
+    }
+    if (p->dry_run) {
+        for (SubHost& h : p->subs) {
+            const SubDev& d = h.dev;
+            p->device_bytes += (int64_t)d.S * d.C * d.NPP * d.N * d.N * 4 + (int64_t)h.ent_ant.size() * (2 + 1 + 8 * d.P) +
+                               (int64_t)h.cell_ptr.size() * 4 + (int64_t)d.C * d.A * d.P * d.K * d.K * 8;
+        }
+        return EPIC_OK;
+    }
+    for (SubHost& h : p->subs) {
+        SubDev& d = h.dev;
+        epic_status s;
+        if ((s = upload(p, &d.chans, h.chans, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.cell_ptr, h.cell_ptr, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.ent_ant, h.ent_ant, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.ent_tap, h.ent_tap, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.cells, h.cells, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.gfrac, h.gfrac, st)) != EPIC_OK) return s;
+        const size_t ntap = (size_t)d.C * d.A * d.P * d.K * d.K * 2;
+        if (!h.user_taps.empty()) {
+            if ((s = upload(p, &d.taps, h.user_taps, st)) != EPIC_OK) return s;
+        } else {
+            if ((s = dalloc(p, &d.taps, ntap)) != EPIC_OK) return s;
+            if ((s = hip_status(launch_gaussian_taps(d, h.desc.kernel_sigma_cells > 0.0 ? h.desc.kernel_sigma_cells : 0.5, st))) != EPIC_OK)
+                return s;
+        }
+        d.gains = nullptr;
+        if ((s = dalloc(p, &d.ent_w, h.ent_ant.size() * 2 * (size_t)d.P)) != EPIC_OK) return s;
+        if ((s = dalloc(p, &d.twiddle, (size_t)d.N)) != EPIC_OK) return s;
+        const size_t nslot = (size_t)d.S * d.C * d.NPP * d.N * d.N;
+        if ((s = dalloc(p, &d.slots, nslot)) != EPIC_OK) return s;
+        if ((s = hip_status(hipMemsetAsync(d.slots, 0, nslot * sizeof(float), st))) != EPIC_OK) return s;
+        if ((s = hip_status(launch_twiddles(d, st))) != EPIC_OK) return s;
+        if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
+    }
+    return hip_status(hipStreamSynchronize(st));
+}
+
+// Live plans; a handle that is not in this set (never created, or already
+// destroyed) is rejected instead of being dereferenced.
+std::mutex g_live_mu;
+std::set<const epic_plan_s*> g_live;
+
+bool valid_plan(epic_plan_t p) {
+    if (p == nullptr) return false;
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.count(p) != 0 && p->magic == kMagic;
+}
+
+void register_plan(epic_plan_t p) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(p);
+}
+
+void unregister_plan(epic_plan_t p) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.erase(p);
+}
+
+epic_status check_device(epic_plan_s* p, hipError_t e) {
+    if (e == hipSuccess) return EPIC_OK;
+    p->sticky = EPIC_E_DEVICE;
+    return EPIC_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t* out) {
+    if (!out) return EPIC_E_ARG;
+    *out = nullptr;
+    if (!desc || desc->n_sub < 1 || desc->n_sub > kMaxSub || !desc->sub) return EPIC_E_ARG;
+    if (desc->precision < EPIC_FP32 || desc->precision > EPIC_FP8) return EPIC_E_ARG;
+    if (desc->gridder < EPIC_GRID_AUTO || desc->gridder > EPIC_GRID_BLOCK_GEMM) return EPIC_E_ARG;
+    if (desc->output != EPIC_OUT_POL && desc->output != EPIC_OUT_STOKES) return EPIC_E_ARG;
+    if (desc->max_time < 1 || desc->device < 0) return EPIC_E_ARG;
+    if (desc->flags & ~kKnownFlags) return EPIC_E_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (desc->reserved[k] != 0) return EPIC_E_ARG;
+    for (int k = 0; k < desc->n_sub; ++k) {
+        epic_status s = validate_sub(desc->sub[k]);
+        if (s != EPIC_OK) return s;
+        if (desc->output == EPIC_OUT_STOKES && desc->sub[k].n_pol != 2) return EPIC_E_ARG;
+    }
+    if (desc->precision != EPIC_FP32) return EPIC_E_UNSUPPORTED;
+    if (desc->gridder != EPIC_GRID_AUTO && desc->gridder != EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
+    if (desc->flags & (EPIC_F_REMOVE_AUTOCORR | EPIC_F_GRAPH | EPIC_F_AUTOTUNE)) return EPIC_E_UNSUPPORTED;
+    epic_plan_s* p = new (std::nothrow) epic_plan_s();
+    if (!p) return EPIC_E_NOMEM;
+    epic_status s;
+    try {
+        s = make_plan(desc, static_cast<hipStream_t>(hip_stream), p);
+    } catch (const std::bad_alloc&) {
+        s = EPIC_E_NOMEM;
+    }
+    if (s != EPIC_OK) {
+        free_all(p);
+        p->magic = 0;
+        delete p;
+        return s;
+    }
+    register_plan(p);
+    *out = p;
+    return EPIC_OK;
+}
+
+epic_status epic_grid_fft_accumulate(epic_plan_t p, const uint8_t* const* d_samples, int64_t n_time,
+                                     void* hip_stream) {
+    if (!valid_plan(p)) return EPIC_E_ARG;
+    if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;
+    if (n_time < 0 || n_time > p->desc.max_time) return EPIC_E_ARG;
+    if (n_time == 0) return EPIC_OK;
+    if (!d_samples) return EPIC_E_ARG;
+    for (size_t k = 0; k < p->subs.size(); ++k)
+        if (!d_samples[k]) return EPIC_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        hipError_t e = launch_fp32(p->subs[k].dev, d_samples[k], n_time, st);
+        if (e != hipSuccess) return check_device(p, e);
+    }
+    return EPIC_OK;
+}
+
+epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, void* hip_stream) {
+    if (!valid_plan(p)) return EPIC_E_ARG;
+    if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;
+    if (!d_images) return EPIC_E_ARG;
+    for (size_t k = 0; k < p->subs.size(); ++k)
+        if (!d_images[k]) return EPIC_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        hipError_t e = launch_readout(p->subs[k].dev, d_images[k], p->desc.output == EPIC_OUT_STOKES, reset != 0, st);
+        if (e != hipSuccess) return check_device(p, e);
+    }
+    return EPIC_OK;
+}
+
+epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, void* hip_stream) {
+    (void)h_gains; (void)hip_stream;
+    if (!valid_plan(p) || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
+    if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;
+    return EPIC_E_UNSUPPORTED;
+}
+
+epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
+    if (!valid_plan(p) || !info) return EPIC_E_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_sub = (int32_t)p->subs.size();
+    info->precision = p->desc.precision;
+    info->gridder = p->desc.gridder;
+    info->output = p->desc.output;
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        const SubDev& d = p->subs[k].dev;
+        info->npp[k] = (p->desc.output == EPIC_OUT_STOKES) ? 4 : d.NPP;
+        info->slots[k] = d.S;
+        info->window_max[k] = std::max(d.Rmax, d.Wmax);
+        info->threads[k] = d.threads;
+        info->lds_bytes[k] = (int64_t)d.lds_bytes;
+    }
+    info->device_bytes = p->device_bytes;
+    return EPIC_OK;
+}
+
+epic_status epic_debug_geometry(epic_plan_t p, int32_t sub, int32_t* h_cells) {
+    if (!valid_plan(p) || !h_cells || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
+    const SubHost& h = p->subs[sub];
+    std::memcpy(h_cells, h.cells.data(), h.cells.size() * sizeof(int32_t));
+    return EPIC_OK;
+}
+
+epic_status epic_debug_unpack(const uint8_t* d_bytes, int64_t n, int32_t nibble_order, float* d_out,
+                              void* hip_stream) {
+    if (!d_bytes || !d_out || n < 0 || (nibble_order != 0 && nibble_order != 1)) return EPIC_E_ARG;
+    if (n == 0) return EPIC_OK;
+    hipError_t e = launch_unpack_debug(d_bytes, n, nibble_order, d_out, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? EPIC_OK : EPIC_E_DEVICE;
+}
+
+epic_status epic_destroy(epic_plan_t p) {
+    if (!p) return EPIC_OK;
+    if (!valid_plan(p)) return EPIC_E_ARG;
+    unregister_plan(p);
+    free_all(p);
+    p->magic = 0;
+    delete p;
+    return EPIC_OK;
+}
+
+const char* epic_status_str(epic_status s) {
+    switch (s) {
+        case EPIC_OK: return "EPIC_OK";
+        case EPIC_E_ARG: return "EPIC_E_ARG";
+        case EPIC_E_GEOMETRY: return "EPIC_E_GEOMETRY";
+        case EPIC_E_NOMEM: return "EPIC_E_NOMEM";
+        case EPIC_E_DEVICE: return "EPIC_E_DEVICE";
+        case EPIC_E_UNSUPPORTED: return "EPIC_E_UNSUPPORTED";
+        case EPIC_E_STATE: return "EPIC_E_STATE";
+    }
+    return "EPIC_E_UNKNOWN";
+}
+
+int32_t epic_abi_version(void) { return EPIC_ABI_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before any side effect, and its FP64
+geometry is bit-identical to the oracle's (dry-run plans touch no device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "epic.h")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2301_09662_amd import epic
+    return epic
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:epic_status|const char\*|int32_t)\s+(epic_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    fns = declared_functions()
+    for f in ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_destroy", "epic_status_str"):
+        assert f in fns
+
+
+def test_library_exports_every_declared_symbol(E):
+    lib = ctypes.CDLL(E.library_path())
+    for f in declared_functions():
+        assert hasattr(lib, f), f
+    assert set(declared_functions()) == set(E.EXPORTED)
+    assert E.epic_abi_version() == 1
+
+
+def test_status_strings(E):
+    names = ["EPIC_OK", "EPIC_E_ARG", "EPIC_E_GEOMETRY", "EPIC_E_NOMEM", "EPIC_E_DEVICE", "EPIC_E_UNSUPPORTED",
+             "EPIC_E_STATE"]
+    for k, n in enumerate(names):
+        assert E.epic_status_str(k) == n
+    assert E.epic_status_str(99) == "EPIC_E_UNKNOWN"
+
+
+def dry(E, subs, **kw):
+    kw.setdefault("max_time", 1000)
+    return E.epic_plan(subs, flags=E.EPIC_F_DRY_RUN | kw.pop("flags", 0), **kw)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 4, 5])
+def test_geometry_bit_exact_with_oracle(E, cfg):
+    wl = synth.workload(cfg)
+    p = dry(E, wl.subs)
+    for k, s in enumerate(wl.subs):
+        cells = E.epic_debug_geometry(p, k)
+        ref, _ = oracle.geometry(s)
+        assert np.array_equal(cells, ref)
+    E.epic_destroy(p)
+
+
+def test_geometry_ties_round_up(E):
+    class S:  # lambda = 1 m, dl = 0.5: x = 0.25 m is exactly half a cell
+        ant_xy = np.array([[0.25, -0.25], [0.75, 0.0], [0.0, 0.0]])
+        n_pol, n_chan, grid_n, grid_dl, freq0_hz, dfreq_hz, kernel_k = 1, 1, 32, 0.5, 299792458.0, 0.0, 3
+    p = dry(E, [S()])
+    assert E.epic_debug_geometry(p, 0)[0].tolist() == [[17, 16], [18, 16], [16, 16]]
+    E.epic_destroy(p)
+
+
+def test_dry_run_query(E):
+    wl = synth.workload(2)
+    p = dry(E, wl.subs)
+    info = E.epic_plan_query(p)
+    assert info["n_sub"] == 1 and info["npp"] == [4]
+    assert info["slots"][0] >= 1 and info["threads"][0] == 256
+    assert 16 <= info["window_max"][0] <= 20          # ~16 lambda aperture + 3-tap kernel
+    assert info["lds_bytes"][0] <= 160 * 1024
+    E.epic_destroy(p)
+
+
+def test_dry_run_refuses_device_work(E):
+    p = dry(E, synth.workload(1).subs)
+    with pytest.raises(E.EpicError) as e:
+        E.epic_grid_fft_accumulate(p, [1 << 20], 1, stream=0)
+    assert e.value.status == E.EPIC_E_STATE
+    with pytest.raises(E.EpicError) as e:
+        E.epic_readout(p, [1 << 20], 0, stream=0)
+    assert e.value.status == E.EPIC_E_STATE
+    E.epic_destroy(p)
+
+
+def test_stale_handle_rejected(E):
+    p = dry(E, synth.workload(1).subs)
+    h = p.handle
+    E.epic_destroy(p)
+    p.handle = h                     # use after destroy
+    with pytest.raises(E.EpicError) as e:
+        E.epic_plan_query(p)
+    assert e.value.status == E.EPIC_E_ARG
+    p.handle = None
+
+
+class Sub:
+    def __init__(self, **kw):
+        self.ant_xy = np.array([[0.0, 0.0], [3.0, -2.0]])
+        self.n_pol, self.n_chan, self.grid_n, self.grid_dl = 2, 2, 32, 0.5
+        self.freq0_hz, self.dfreq_hz, self.kernel_k = 40e6, 25e3, 3
+        self.__dict__.update(kw)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n_pol=3), "ARG"), (dict(n_chan=0), "ARG"), (dict(grid_n=40), "ARG"), (dict(grid_n=256), "ARG"),
+    (dict(kernel_k=2), "ARG"), (dict(kernel_k=9), "ARG"), (dict(grid_dl=0.0), "ARG"), (dict(grid_dl=np.nan), "ARG"),
+    (dict(freq0_hz=-1.0), "ARG"), (dict(dfreq_hz=-1.0), "ARG"),
+    (dict(ant_xy=np.array([[0.0, np.inf]])), "ARG"),
+    (dict(ant_xy=np.array([[60.0, 0.0]])), "GEOMETRY"),          # 60 m at 40 MHz, dl 0.5 -> cell 32 of 32
+    (dict(ant_xy=np.zeros((40000, 2))), "ARG"),                    # A * P > 65536
+])
+def test_validation(E, bad, code):
+    with pytest.raises(E.EpicError) as e:
+        dry(E, [Sub(**bad)])
+    assert e.value.status == getattr(E, "EPIC_E_" + code)
+
+
+def test_plan_level_validation(E):
+    s = [Sub()]
+    for kw, code in [(dict(max_time=0), "ARG"), (dict(precision=7), "ARG"), (dict(gridder=9), "ARG"),
+                     (dict(output=5), "ARG"), (dict(reserved=(0, 1, 0, 0)), "ARG"), (dict(flags=1 << 20), "ARG"),
+                     (dict(device=-1), "ARG")]:
+        with pytest.raises(E.EpicError) as e:
+            dry(E, s, **kw)
+        assert e.value.status == getattr(E, "EPIC_E_" + code), kw
+    with pytest.raises(E.EpicError):
+        dry(E, [])
+    # Stokes output needs two polarisations
+    with pytest.raises(E.EpicError) as e:
+        dry(E, [Sub(n_pol=1)], output=E.EPIC_OUT_STOKES)
+    assert e.value.status == E.EPIC_E_ARG
+
+
+def test_geometry_at_the_edge_is_accepted(E):
+    # footprint exactly touching cells 0 and N-1
+    lam = 299792458.0 / 40e6
+    xy = np.array([[-15 * 0.5 * lam, 0.0], [14 * 0.5 * lam, 0.0]])
+    p = dry(E, [Sub(ant_xy=xy, n_chan=1, dfreq_hz=0.0)])
+    cells = E.epic_debug_geometry(p, 0)
+    assert cells[0, :, 0].tolist() == [1, 30]
+    E.epic_destroy(p)
+
+
+def test_debug_calls_validate(E):
+    with pytest.raises(E.EpicError) as e:
+        E.epic_debug_unpack(0, 16, 0, 0, stream=0)
+    assert e.value.status == E.EPIC_E_ARG
+    with pytest.raises(E.EpicError) as e:
+        E.epic_debug_unpack(1 << 20, -1, 0, 1 << 20, stream=0)
+    assert e.value.status == E.EPIC_E_ARG

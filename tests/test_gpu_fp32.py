@@ -1,0 +1,156 @@
+"""GPU parity of the FP32 hot path against the FP64 oracle, through the C ABI.
+
+Tolerance: 1e-5 per image, both as relative Frobenius error and as max |diff|
+over the channel's image peak.  FP32 transforms of these sizes are accurate to
+~1e-7 relative and the per-slot time sums of at most a few hundred positive
+terms add ~1e-6, so 1e-5 leaves an order of magnitude of margin.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_parity, run_library, torch_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2301_09662_amd import epic
+    return epic
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_unpack_bit_exact(E, order):
+    torch, dev = torch_dev()
+    codes = torch.arange(256, dtype=torch.uint8, device=dev)
+    out = torch.empty((256, 2), dtype=torch.float32, device=dev)
+    E.epic_debug_unpack(codes, 256, order, out)
+    torch.cuda.synchronize()
+    re, im = oracle.unpack_table(order)
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:, 0], re) and np.array_equal(got[:, 1], im)
+
+
+def test_tiny_config_full(E):
+    """Config 1: 16 single-pol antennas, 4 channels, N=32, 64 spectra."""
+    sub = synth.workload(1).subs[0]
+    x = synth.samples(sub, 64)
+    (gpu,), info = run_library(E, [sub], [x])
+    assert_parity(gpu, oracle.image(sub, x), TOL, "cfg1")
+
+
+def test_station_subset_several_tiles(E):
+    """Station layout (256 dual-pol antennas, N=64), 6 channels, 37 spectra:
+    a ragged time split over the slots."""
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=6)
+    x = synth.samples(sub, 37)
+    (gpu,), info = run_library(E, [sub], [x])
+    assert info["slots"][0] > 1
+    assert_parity(gpu, oracle.image(sub, x), TOL, "cfg2-subset")
+
+
+@pytest.mark.parametrize("cfg,k,nchan,T", [(4, 1, 3, 20), (4, 2, 2, 12), (4, 0, 2, 16), (5, 0, 2, 6)])
+def test_other_grid_sizes(E, cfg, k, nchan, T):
+    """N = 48 (radix-3 folding), 96 and 128 (column split over two workgroups)."""
+    sub = synth.shrink(synth.workload(cfg).subs[k], n_chan=nchan)
+    x = synth.samples(sub, T)
+    (gpu,), _ = run_library(E, [sub], [x])
+    assert_parity(gpu, oracle.image(sub, x), TOL, f"cfg{cfg}.{k}")
+
+
+def test_split_calls_and_readout_without_reset(E):
+    """Three calls (13 + 1 + 6 spectra) equal one call of 20; reading out
+    without reset then with reset keeps the sum."""
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=3)
+    x = synth.samples(sub, 20)
+    ora = oracle.image(sub, x)
+    (g1,), _ = run_library(E, [sub], [x], calls=[13, 1, 6])
+    assert_parity(g1, ora, TOL, "split")
+    (g2,), _ = run_library(E, [sub], [x], calls=[20], readout_reset=False)
+    assert_parity(g2, ora, TOL, "no-reset")
+
+
+def test_reset_and_empty_calls(E):
+    torch, dev = torch_dev()
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    x = torch.from_numpy(synth.samples(sub, 8)).to(dev)
+    plan = E.epic_plan([sub], max_time=8)
+    try:
+        out = torch.empty((2, 4, 64, 64), dtype=torch.float32, device=dev)
+        E.epic_grid_fft_accumulate(plan, [x], 0)          # no-op
+        E.epic_readout(plan, [out], 1)
+        torch.cuda.synchronize()
+        assert float(out.abs().max()) == 0.0
+        E.epic_grid_fft_accumulate(plan, [x], 8)
+        E.epic_readout(plan, [out], 1)
+        E.epic_readout(plan, [out], 1)                    # after reset: zero
+        torch.cuda.synchronize()
+        assert float(out.abs().max()) == 0.0
+        with pytest.raises(E.EpicError) as e:
+            E.epic_grid_fft_accumulate(plan, [x], 9)      # beyond max_time
+        assert e.value.status == E.EPIC_E_ARG
+    finally:
+        E.epic_destroy(plan)
+
+
+def test_deterministic(E):
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=4)
+    x = synth.samples(sub, 25)
+    (a,), _ = run_library(E, [sub], [x])
+    (b,), _ = run_library(E, [sub], [x])
+    assert np.array_equal(a, b)
+
+
+def test_single_pol_swapped_nibbles_user_taps(E):
+    """Single pol, nibble order 1, complex user taps."""
+    sub = synth.shrink(synth.workload(1).subs[0], n_chan=3)
+    x = synth.samples(sub, 16)
+    rng = np.random.default_rng(8)
+    taps = rng.standard_normal((3, 16, 1, 3, 3, 2)).astype(np.float32)
+    (gpu,), _ = run_library(E, [sub], [x], taps=[taps], nibble_order=1)
+    assert_parity(gpu, oracle.image(sub, x, taps=taps, nibble_order=1), TOL, "user-taps")
+
+
+def test_dual_pol_user_taps_and_multi_sub(E):
+    """Two sub-arrays in one plan, per-pol complex taps on the first."""
+    s1 = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=100)
+    s2 = synth.shrink(synth.workload(4).subs[1], n_chan=3)
+    x1, x2 = synth.samples(s1, 10), synth.samples(s2, 10)
+    taps = np.random.default_rng(9).standard_normal((2, 100, 2, 3, 3, 2)).astype(np.float32)
+    (g1, g2), _ = run_library(E, [s1, s2], [x1, x2], taps=[taps, None])
+    assert_parity(g1, oracle.image(s1, x1, taps=taps), TOL, "sub0")
+    assert_parity(g2, oracle.image(s2, x2), TOL, "sub1")
+
+
+def test_single_antenna_and_edge_footprint(E):
+    """Degenerate arrays: one antenna; two antennas whose kernels touch cells
+    0 and N-1 (the window spans the whole grid)."""
+    lam = 299792458.0 / 40e6
+
+    class S:
+        n_pol, n_chan, grid_n, grid_dl, freq0_hz, dfreq_hz, kernel_k = 2, 1, 32, 0.5, 40e6, 0.0, 3
+    edge = np.array([[-15 * 0.5 * lam, -15 * 0.5 * lam], [14 * 0.5 * lam, 14 * 0.5 * lam]])
+    for k, xy in enumerate((np.array([[1.3, -2.2]]), edge)):
+        s = S()
+        s.ant_xy = xy
+        x = np.random.default_rng(k).integers(0, 256, (7, 1, len(xy), 2), dtype=np.uint8)
+        (gpu,), _ = run_library(E, [s], [x])
+        assert_parity(gpu, oracle.image(s, x), TOL, f"edge{len(xy)}")
+
+
+def test_full_station_sampled_channels(E):
+    """Config 2 at full size in the benchmark's launch shape (132 channels,
+    1000 spectra in one call), compared on three channels the oracle computes."""
+    sub = synth.workload(2).subs[0]
+    x = synth.samples(sub, 1000)
+    (gpu,), info = run_library(E, [sub], [x])
+    for c in (0, 77, 131):
+        ora = oracle.image(sub, x, chans=range(c, c + 1))
+        assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"cfg2 full, channel {c}")
+    # every channel: finite, non-negative XX/YY, Cauchy-Schwarz
+    assert np.isfinite(gpu).all()
+    assert (gpu[:, 0] >= 0).all() and (gpu[:, 1] >= 0).all()
+    assert (gpu[:, 2] ** 2 + gpu[:, 3] ** 2 <= gpu[:, 0] * gpu[:, 1] * (1 + 1e-4) + 1e-3).all()
