@@ -66,4 +66,24 @@ __device__ __forceinline__ void fft16(float2 (&z)[16]) {
     for (int m1 = 0; m1 < 4; ++m1) dft4(z[4 * m1], z[4 * m1 + 1], z[4 * m1 + 2], z[4 * m1 + 3]);
 }
 
+// In-place 8-point DFT X[m] = sum_n z[n] exp(+2 pi i n m / 8), as 4 x 2
+// (n = 2 n1 + n2, m = m1 + 4 m2).  On return X[m] is held in z[fft8_pos(m)].
+__device__ __forceinline__ constexpr int fft8_pos(int m) { return 2 * (m & 3) + (m >> 2); }
+
+__device__ __forceinline__ void fft8(float2 (&z)[8]) {
+    constexpr float h = 0.707106781186547524f;   // cos(pi/4)
+    dft4(z[0], z[2], z[4], z[6]);   // n2 = 0: z[2 m1] = A0[m1]
+    dft4(z[1], z[3], z[5], z[7]);   // n2 = 1: z[2 m1 + 1] = A1[m1]
+    // A1[m1] *= exp(+2 pi i m1 / 8)
+    z[3] = make_float2(h * (z[3].x - z[3].y), h * (z[3].x + z[3].y));     // W^1
+    z[5] = make_float2(-z[5].y, z[5].x);                                  // W^2 = i
+    z[7] = make_float2(-h * (z[7].x + z[7].y), h * (z[7].x - z[7].y));    // W^3
+#pragma unroll
+    for (int m1 = 0; m1 < 4; ++m1) {
+        const float2 a = z[2 * m1], b = z[2 * m1 + 1];
+        z[2 * m1] = cadd(a, b);          // X[m1]
+        z[2 * m1 + 1] = csub(a, b);      // X[m1 + 4]
+    }
+}
+
 }  // namespace epic

@@ -20,28 +20,43 @@ constexpr int kMaxGridN = 128;
 // multiplies both polarisations' sky fields by the same unit phase, the
 // products of Eq. 5 do not depend on where the window sits in the grid; the
 // kernels place it at the origin.
+//
+// Gridding runs as a "gather program": the non-empty window cells, sorted by
+// their number of contributions (so neighbouring lanes loop equally long),
+// each with a list of (antenna, tap) contributions padded with zero-weight
+// entries to whole groups of kGroup.
+constexpr int kGroup = 4;
+
 struct ChanInfo {
     int32_t x0, y0;      // absolute cell of window element (0, 0)
     int32_t R, W;        // window rows (y extent) and columns (x extent)
-    int32_t cell_off;    // offset of this channel's cell_ptr block (R*W + 1 words)
-    int32_t ent_off;     // offset of this channel's first gather entry
-    int32_t n_ent;       // entries of this channel (A * K * K)
-    int32_t pad;
+    int32_t n_cell;      // non-empty cells
+    int32_t cell_off;    // offset of this channel's cell descriptors
+    int32_t n_grp;       // groups of kGroup entries
+    int32_t grp_off;     // offset of this channel's first group
 };
+
+// Cell descriptor: x = LDS float2 offset of the cell within one pol's window
+// (row * pitch + col) | (groups << 16); y = first group (channel-relative).
+using CellDesc = uint2;
 
 // Device resources of one sub-array.
 struct SubDev {
     // shape
     int A, P, C, N, K, NPP, nibble_order;
-    int S;               // time slots (partial accumulators)
+    int S;               // partial accumulator slots per channel
     int KS;              // column split of the image across workgroups
-    int Rmax, Wmax, Emax;  // largest window / entry count over channels
+    int Rmax, Wmax;      // largest window over channels
+    int WP;              // LDS row pitch (float2) of the gridded window
+    int Gmax, CellMax;   // largest group / non-empty cell count over channels
+    int real_taps;       // every tap (and gain) is real: one float per pol per entry
+    int grid_wg;         // resident workgroups of one launch (persistent)
     // tables
     ChanInfo* chans;          // [C]
-    uint32_t* cell_ptr;       // per channel [R*W + 1], entry offsets relative to ent_off
-    uint16_t* ent_ant;        // [sum n_ent] antenna of each gather entry
-    uint8_t* ent_tap;         // [sum n_ent] tap index dy*K + dx
-    float* ent_w;             // [sum n_ent][2P] weight of each entry per pol (re, im)
+    CellDesc* cells_desc;     // [sum n_cell]
+    uint16_t* grp_ant;        // [sum n_grp * kGroup] antenna per entry (0 for padding)
+    uint8_t* grp_tap;         // [sum n_grp * kGroup] tap dy*K+dx, 255 for padding
+    float* grp_w;             // [sum n_grp * kGroup][WF] entry weights, WF = P (real) or 2P
     int32_t* cells;           // [C][A][2] nearest cell
     double* gfrac;            // [C][A][2] fractional cell coordinate
     float* taps;              // [C][A][P][K][K][2] FP32 taps (before gains)
@@ -51,7 +66,7 @@ struct SubDev {
     // launch shape
     int threads;
     size_t lds_bytes;
-    int csr_in_lds;
+    int prog_lds;        // gather program copied to LDS (else read through L2)
 };
 
 // ---- launchers (defined in the .hip translation units) -----------------
@@ -62,7 +77,8 @@ hipError_t launch_twiddles(const SubDev& d, hipStream_t st);
 hipError_t launch_entry_weights(const SubDev& d, hipStream_t st);
 
 // The FP32 hot path for one sub-array: n_time spectra of uint8 [T][C][A][P].
-hipError_t fp32_configure(SubDev& d, int device);
+// fp32_configure picks the launch shape; with device < 0 it makes no HIP call.
+hipError_t fp32_configure(SubDev& d, int device, int num_cu);
 hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 
 // Ordered reduction of the slots into [C][NPP][N][N] (or Stokes), optional reset.

@@ -47,30 +47,41 @@ __global__ void twiddle_kernel(float2* __restrict__ tw, int N) {
 }
 
 // Weight of every gather entry: the entry's tap times the antenna's gain,
-// complex product in FP64, rounded once.  One thread per entry.
-__global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const uint16_t* __restrict__ ent_ant,
-                                     const uint8_t* __restrict__ ent_tap, const float* __restrict__ taps,
-                                     const float* __restrict__ gains, float* __restrict__ ent_w, int C, int A,
-                                     int P, int K, int Emax) {
+// complex product in FP64, rounded once.  Padding entries (tap 255) weigh 0.
+// Layout per entry: real taps -> P floats (re per pol); complex -> 2P floats.
+// One thread per entry slot of one channel.
+__global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const uint16_t* __restrict__ grp_ant,
+                                     const uint8_t* __restrict__ grp_tap, const float* __restrict__ taps,
+                                     const float* __restrict__ gains, float* __restrict__ grp_w, int C, int A,
+                                     int P, int K, int real) {
     const int c = blockIdx.y;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     const ChanInfo ci = chans[c];
-    if (e >= ci.n_ent) return;
-    const int64_t ge = (int64_t)ci.ent_off + e;
-    const int a = ent_ant[ge], tap = ent_tap[ge];
+    if (e >= ci.n_grp * kGroup) return;
+    const int64_t ge = (int64_t)ci.grp_off * kGroup + e;
+    const int a = grp_ant[ge], tap = grp_tap[ge];
+    const int wf = real ? P : 2 * P;
     for (int p = 0; p < P; ++p) {
-        const int64_t ti = ((((int64_t)c * A + a) * P + p) * K * K + tap) * 2;
-        double wr = taps[ti], wi = taps[ti + 1];
-        if (gains) {
-            const int64_t gi = (((int64_t)c * A + a) * P + p) * 2;
-            const double gr = gains[gi], gim = gains[gi + 1];
-            const double r = gr * wr - gim * wi, i = gr * wi + gim * wr;
-            wr = r;
-            wi = i;
+        double wr = 0.0, wi = 0.0;
+        if (tap != 255) {
+            const int64_t ti = ((((int64_t)c * A + a) * P + p) * K * K + tap) * 2;
+            wr = taps[ti];
+            wi = taps[ti + 1];
+            if (gains) {
+                const int64_t gi = (((int64_t)c * A + a) * P + p) * 2;
+                const double gr = gains[gi], gim = gains[gi + 1];
+                const double r = gr * wr - gim * wi, i = gr * wi + gim * wr;
+                wr = r;
+                wi = i;
+            }
         }
-        ent_w[ge * 2 * P + 2 * p + 0] = (float)wr;
-        ent_w[ge * 2 * P + 2 * p + 1] = (float)wi;
+        if (real) {
+            grp_w[ge * wf + p] = (float)wr;
+        } else {
+            grp_w[ge * wf + 2 * p + 0] = (float)wr;
+            grp_w[ge * wf + 2 * p + 1] = (float)wi;
+        }
     }
 }
 
@@ -119,8 +130,8 @@ hipError_t launch_twiddles(const SubDev& d, hipStream_t st) {
 
 hipError_t launch_entry_weights(const SubDev& d, hipStream_t st) {
     const int bs = 256;
-    entry_weights_kernel<<<dim3((d.Emax + bs - 1) / bs, d.C), dim3(bs), 0, st>>>(
-        d.chans, d.ent_ant, d.ent_tap, d.taps, d.gains, d.ent_w, d.C, d.A, d.P, d.K, d.Emax);
+    entry_weights_kernel<<<dim3((d.Gmax * kGroup + bs - 1) / bs, d.C), dim3(bs), 0, st>>>(
+        d.chans, d.grp_ant, d.grp_tap, d.taps, d.gains, d.grp_w, d.C, d.A, d.P, d.K, d.real_taps);
     return hipGetLastError();
 }
 

@@ -1,22 +1,25 @@
-// FP32 hot path: one fused kernel per sub-array that, for each (channel, time
-// slot) work item, loops over its spectra and for each spectrum
+// FP32 hot path: one persistent fused kernel per sub-array.  Each workgroup
+// takes an equal, contiguous run of the (channel, spectrum) sequence and, for
+// each spectrum,
 //   1. decodes the A*P 4+4-bit samples into LDS                 (Sec. 2.1)
-//   2. grids them by gathering, per aperture cell, the weighted samples of
-//      every antenna whose kernel covers the cell                (Eq. 4, Sec. 3.1)
+//   2. grids them by gathering, per non-empty aperture cell, the weighted
+//      samples of every antenna whose kernel covers the cell     (Eq. 4, Sec. 3.1)
 //   3. transforms the aperture window along x (rows), then along y (columns),
 //      with exp(+2 pi i ...) N-point DFTs                        (Eq. 4)
 //   4. forms XX*, YY*, Re XY*, Im XY* per pixel and adds them into registers
 //                                                               (Eq. 5, Sec. 3.2)
-// and finally adds the registers into its slot of the partial accumulators.
+// and when its run leaves a channel (or ends) adds the registers into that
+// channel's partial-accumulator slot.  Slots are summed in a fixed order by
+// the read-out, so results are bitwise reproducible.
 //
-// Transform layout.  N = 16 Q.  Every N-point DFT is split as
-//   X[q + Q m] = sum_{n1<16} w_N^{n1 q} [ sum_{n2} v[n1 + 16 n2] w_Q^{n2 q} ] w_16^{n1 m},
+// Transform layout.  N = 8 Q.  Every N-point DFT is split as
+//   X[q + Q m] = sum_{n1<8} w_N^{n1 q} [ sum_{n2} v[n1 + 8 n2] w_Q^{n2 q} ] w_8^{n1 m},
 // so lane (q, k) folds its input column with per-lane twiddles and finishes
-// with a register 16-point DFT, producing the 16 outputs j = q + Q m.  Only the
+// with a register 8-point DFT, producing the 8 outputs j = q + Q m.  Only the
 // R x W aperture window is non-zero, so the row pass runs on R rows only and
 // both passes fold just R (or W) inputs.  The column pass leaves each pixel's
 // X and Y values in the same lane, so the products and the time accumulation
-// never leave registers: 16 pixels x 4 products per lane.
+// never leave registers: 8 pixels x 4 products per lane.
 //
 // The window sits at the grid origin instead of at its absolute cells, and the
 // (-1)^(x+y) image-centring factor is replaced by reading bin (i + N/2) mod N
@@ -36,155 +39,258 @@ struct Fp32Args {
     int64_t T;
     int C, A, S;
     const ChanInfo* chans;
-    const uint32_t* cell_ptr;
-    const uint16_t* ent_ant;
-    const float* ent_w;
+    const CellDesc* cells_desc;
+    const uint2* grp_ant;     // 4 x u16 per group
+    const float4* grp_w;      // weights per group (1, 2 or 4 float4)
     const float2* twiddle;    // [N]
     float* slots;             // [S][C][NPP][N][N]
     int Rmax, WP, YP;
-    uint32_t off_w, off_smp, off_G, off_Y, off_cp, off_ant;
+    uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
     int nibble_order;
-    int units, units_per_xcd;
+    int grid_wg, wg_per_xcd;
 };
 
-template <int Q>
+template <int N_>
 struct Shape {
-    static constexpr int N = 16 * Q;
-    static constexpr int KS = (Q >= 7) ? 2 : 1;        // image columns split over KS workgroups
-    static constexpr int NK = N / KS;                  // columns per workgroup
-    static constexpr int LANES = Q * NK;               // (q, column) lanes
+    static constexpr int N = N_;
+    static constexpr int Q = N / 8;                            // lanes per image column
+    static constexpr int KS = (Q * N > 1024) ? 2 : 1;          // image columns split over KS workgroups
+    static constexpr int NK = N / KS;                          // columns per workgroup
+    static constexpr int LANES = Q * NK;                       // (q, column) lanes
     static constexpr int THREADS = ((LANES + 63) / 64) * 64;
 };
 
-// z[n1] = w_N^{n1 q} * sum_{n2} v[(n1 + 16 n2) * stride] * w_Q^{n2 q}, for the
-// first `len` inputs (the rest are zero).  `len` is uniform across the block.
-template <int Q>
-__device__ __forceinline__ void fold_twiddle(float2 (&z)[16], const float2* __restrict__ v, int stride, int len,
-                                             const float2 (&tw)[16], const float2 (&wq)[Q]) {
+constexpr int kPrefetch = 4;   // sample words per thread held in registers ahead of use
+
+// ---- DFT input fold ---------------------------------------------------------
+// z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * stride] * w_Q^{n2 q}.
+// The window is zero-padded to whole blocks of 8, so every block is full and
+// the only control flow is the uniform block count nb.  s_tw is the LDS table
+// exp(+2 pi i r / N); tw holds w_N^{n1 q}.
+template <int N>
+__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int stride, int nb,
+                                             const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) {
-        float2 s = make_float2(0.f, 0.f);
-        if (n1 < len) s = v[n1 * stride];
+    for (int k = 0; k < 8; ++k) z[k] = v[k * stride];
+    int widx = 0;   // (8 n2 q) mod N
+    // not unrolled: an unrolled loop lets the compiler hoist every block's LDS
+    // loads above the exit test, which costs ~100 registers
+#pragma unroll 1
+    for (int n2 = 1; n2 < nb; ++n2) {
+        widx += 8 * q;
+        if (widx >= N) widx -= N;
+        const float2 w = s_tw[widx];
+        const float2* vb = v + 8 * n2 * stride;
 #pragma unroll
-        for (int n2 = 1; n2 < Q; ++n2) {
-            const int n = n1 + 16 * n2;
-            if (n < len) s = cfma(s, v[n * stride], wq[n2]);
+        for (int k = 0; k < 8; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+    }
+#pragma unroll
+    for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], tw[n1]);   // tw[0] = 1
+}
+
+// ---- gather gridding of one group of kGroup entries ------------------------
+template <int P, bool REAL>
+__device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float4* __restrict__ w,
+                                             const uint2 ia, const float2* __restrict__ smp) {
+    const int a[4] = {(int)(ia.x & 0xFFFFu), (int)(ia.x >> 16), (int)(ia.y & 0xFFFFu), (int)(ia.y >> 16)};
+    if constexpr (P == 2) {
+        const float4* s4 = reinterpret_cast<const float4*>(smp);
+        const float4 s0 = s4[a[0]], s1 = s4[a[1]], s2 = s4[a[2]], s3 = s4[a[3]];
+        if constexpr (REAL) {
+            const float4 w01 = w[0], w23 = w[1];   // (w0x, w0y, w1x, w1y), (w2x, w2y, w3x, w3y)
+            gx.x = fmaf(w01.x, s0.x, gx.x); gx.y = fmaf(w01.x, s0.y, gx.y);
+            gy.x = fmaf(w01.y, s0.z, gy.x); gy.y = fmaf(w01.y, s0.w, gy.y);
+            gx.x = fmaf(w01.z, s1.x, gx.x); gx.y = fmaf(w01.z, s1.y, gx.y);
+            gy.x = fmaf(w01.w, s1.z, gy.x); gy.y = fmaf(w01.w, s1.w, gy.y);
+            gx.x = fmaf(w23.x, s2.x, gx.x); gx.y = fmaf(w23.x, s2.y, gx.y);
+            gy.x = fmaf(w23.y, s2.z, gy.x); gy.y = fmaf(w23.y, s2.w, gy.y);
+            gx.x = fmaf(w23.z, s3.x, gx.x); gx.y = fmaf(w23.z, s3.y, gx.y);
+            gy.x = fmaf(w23.w, s3.z, gy.x); gy.y = fmaf(w23.w, s3.w, gy.y);
+        } else {
+            const float4 ww[4] = {w[0], w[1], w[2], w[3]};   // (wxr, wxi, wyr, wyi) per entry
+            const float4 ss[4] = {s0, s1, s2, s3};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                gx = cfma(gx, make_float2(ww[e].x, ww[e].y), make_float2(ss[e].x, ss[e].y));
+                gy = cfma(gy, make_float2(ww[e].z, ww[e].w), make_float2(ss[e].z, ss[e].w));
+            }
         }
-        z[n1] = cmul(s, tw[n1]);
+    } else {
+        const float2 s0 = smp[a[0]], s1 = smp[a[1]], s2 = smp[a[2]], s3 = smp[a[3]];
+        if constexpr (REAL) {
+            const float4 ww = w[0];
+            gx.x = fmaf(ww.x, s0.x, gx.x); gx.y = fmaf(ww.x, s0.y, gx.y);
+            gx.x = fmaf(ww.y, s1.x, gx.x); gx.y = fmaf(ww.y, s1.y, gx.y);
+            gx.x = fmaf(ww.z, s2.x, gx.x); gx.y = fmaf(ww.z, s2.y, gx.y);
+            gx.x = fmaf(ww.w, s3.x, gx.x); gx.y = fmaf(ww.w, s3.y, gx.y);
+        } else {
+            const float4 w01 = w[0], w23 = w[1];
+            gx = cfma(gx, make_float2(w01.x, w01.y), s0);
+            gx = cfma(gx, make_float2(w01.z, w01.w), s1);
+            gx = cfma(gx, make_float2(w23.x, w23.y), s2);
+            gx = cfma(gx, make_float2(w23.z, w23.w), s3);
+        }
     }
 }
 
-template <int Q, int P, bool CSR_LDS>
-__global__ void __launch_bounds__(Shape<Q>::THREADS) fp32_kernel(Fp32Args a) {
-    using Sh = Shape<Q>;
-    constexpr int N = Sh::N, KS = Sh::KS, NK = Sh::NK, LANES = Sh::LANES, THREADS = Sh::THREADS;
+template <int P, bool REAL>
+constexpr int group_f4() {   // float4 words of weights per group
+    return REAL ? (P == 2 ? 2 : 1) : (P == 2 ? 4 : 2);
+}
+
+template <int N_, int P, bool REAL, bool PROG_LDS>
+__global__ void __launch_bounds__(Shape<N_>::THREADS) fp32_kernel(Fp32Args a) {
+    using Sh = Shape<N_>;
+    constexpr int N = Sh::N, Q = Sh::Q, KS = Sh::KS, NK = Sh::NK, LANES = Sh::LANES, THREADS = Sh::THREADS;
     constexpr int NPP = (P == 2) ? 4 : 1;
+    constexpr int GF4 = group_f4<P, REAL>();
     const int tid = threadIdx.x;
 
-    // XCD-aware work item: consecutive items (same channel) share an XCD's L2.
+    // Persistent, XCD-aware: consecutive runs (mostly the same channel) share
+    // an XCD and its L2.
     const int b = blockIdx.x;
-    const int u = (b & 7) * a.units_per_xcd + (b >> 3);
-    if (u >= a.units) return;
-    const int kpart = u % KS;
-    const int cs = u / KS;
-    const int s = cs % a.S;
-    const int c = cs / a.S;
-    const int64_t t0 = ((int64_t)s * a.T) / a.S;
-    const int64_t t1 = ((int64_t)(s + 1) * a.T) / a.S;
-    if (t0 >= t1) return;
+    const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
+    if (g >= a.grid_wg) return;
+    const int64_t T = a.T;
+    const int64_t total = (int64_t)a.C * KS * T;
+    const int64_t L = (total + a.grid_wg - 1) / a.grid_wg;
+    const int64_t f0 = (int64_t)g * L;
+    const int64_t f1 = (f0 + L < total) ? f0 + L : total;
+    if (f0 >= f1) return;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    float* s_w = reinterpret_cast<float*>(smem + a.off_w);
+    float4* s_w = reinterpret_cast<float4*>(smem + a.off_w);
+    uint2* s_gant = reinterpret_cast<uint2*>(smem + a.off_gant);
+    uint2* s_desc = reinterpret_cast<uint2*>(smem + a.off_desc);
     float2* s_smp = reinterpret_cast<float2*>(smem + a.off_smp);
     float2* s_G = reinterpret_cast<float2*>(smem + a.off_G);
     float2* s_Y = reinterpret_cast<float2*>(smem + a.off_Y);
-    uint32_t* s_cp = reinterpret_cast<uint32_t*>(smem + a.off_cp);
-    uint16_t* s_ant = reinterpret_cast<uint16_t*>(smem + a.off_ant);
+    float2* s_tw = reinterpret_cast<float2*>(smem + a.off_tw);
+    for (int k = tid; k < N; k += THREADS) s_tw[k] = a.twiddle[k];
 
-    const ChanInfo ci = a.chans[c];
-    const int R = ci.R, W = ci.W, cellsN = R * W;
-    const int AP = a.A * P;
-
-    const uint32_t* cp = a.cell_ptr + ci.cell_off;
-    const uint16_t* ant = a.ent_ant + ci.ent_off;
-    const float* wts = a.ent_w + (int64_t)ci.ent_off * 2 * P;
-    if constexpr (CSR_LDS) {
-        // one (re, im) pair per pol per entry: float4 for dual pol (16-byte
-        // aligned since entry offsets are whole entries), float2 for single pol
-        if constexpr (P == 2) {
-            const float4* src = reinterpret_cast<const float4*>(wts);
-            float4* dst = reinterpret_cast<float4*>(s_w);
-            for (int k = tid; k < ci.n_ent; k += THREADS) dst[k] = src[k];
-        } else {
-            const float2* src = reinterpret_cast<const float2*>(wts);
-            float2* dst = reinterpret_cast<float2*>(s_w);
-            for (int k = tid; k < ci.n_ent; k += THREADS) dst[k] = src[k];
-        }
-        for (int k = tid; k <= cellsN; k += THREADS) s_cp[k] = cp[k];
-        for (int k = tid; k < ci.n_ent; k += THREADS) s_ant[k] = ant[k];
-    }
-
-    // per-lane transform constants
+    // per-lane transform constants (q is wave-uniform when a wave holds one q)
     const bool lane_on = tid < LANES;
-    const int q = lane_on ? tid / NK : 0;
+    int q = lane_on ? tid / NK : 0;
+    if constexpr (NK % 64 == 0) q = __builtin_amdgcn_readfirstlane(q);
     const int kk = lane_on ? tid - q * NK : 0;
-    float2 tw[16], wq[Q];
+    float2 tw[8];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) tw[n1] = a.twiddle[(n1 * q) % N];
-#pragma unroll
-    for (int n2 = 0; n2 < Q; ++n2) wq[n2] = a.twiddle[(16 * n2 * q) % N];
+    for (int n1 = 0; n1 < 8; ++n1) tw[n1] = a.twiddle[(n1 * q) % N];
 
-    float acc[16][NPP];
-#pragma unroll
-    for (int m = 0; m < 16; ++m)
-#pragma unroll
-        for (int k = 0; k < NPP; ++k) acc[m][k] = 0.f;
-
+    const int AP = a.A * P;
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.samples) & 3) == 0);
+    const int nwords = AP >> 2;
 
-    for (int64_t t = t0; t < t1; ++t) {
-        // 1. decode the (t, c) row of A*P bytes
-        const uint8_t* row = a.samples + ((int64_t)t * a.C + c) * AP;
-        if (words) {
-            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(row);
-            for (int w = tid; w < (AP >> 2); w += THREADS) {
-                const uint32_t v = row4[w];
-                s_smp[4 * w + 0] = unpack44(v & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 1] = unpack44((v >> 8) & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 2] = unpack44((v >> 16) & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 3] = unpack44(v >> 24, a.nibble_order);
-            }
-        } else {
-            for (int k = tid; k < AP; k += THREADS) s_smp[k] = unpack44(row[k], a.nibble_order);
+    float acc[8][NPP];
+    int v = (int)(f0 / T);
+    int64_t t = f0 - (int64_t)v * T;
+    int cur_v = -1, c = 0, kpart = 0, slot = 0, R = 0, W = 0, n_cell = 0, nbR = 0, nbW = 0;
+    const CellDesc* g_desc = nullptr;
+    const uint2* g_gant = nullptr;
+    const float4* g_w = nullptr;
+
+    uint32_t pre[kPrefetch];
+    auto prefetch = [&](int vv, int64_t tt) {
+        const int cc = vv / KS;
+        const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
+#pragma unroll
+        for (int k = 0; k < kPrefetch; ++k) {
+            const int w = tid + k * THREADS;
+            pre[k] = (w < nwords) ? row4[w] : 0u;
         }
-        __syncthreads();
+    };
+    if (words) prefetch(v, t);
 
-        // 2. gather gridding of the R x W window, both pols per cell
-        for (int cell = tid; cell < cellsN; cell += THREADS) {
-            const int r = cell / W, w = cell - r * W;
-            uint32_t e0, e1;
-            if constexpr (CSR_LDS) { e0 = s_cp[cell]; e1 = s_cp[cell + 1]; }
-            else { e0 = cp[cell]; e1 = cp[cell + 1]; }
-            float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
-            for (uint32_t e = e0; e < e1; ++e) {
-                int an;
-                if constexpr (CSR_LDS) an = s_ant[e]; else an = ant[e];
-                if constexpr (P == 2) {
-                    float4 wt;
-                    if constexpr (CSR_LDS) wt = reinterpret_cast<const float4*>(s_w)[e];
-                    else wt = reinterpret_cast<const float4*>(wts)[e];
-                    const float4 sv = reinterpret_cast<const float4*>(s_smp)[an];
-                    gx = cfma(gx, make_float2(wt.x, wt.y), make_float2(sv.x, sv.y));
-                    gy = cfma(gy, make_float2(wt.z, wt.w), make_float2(sv.z, sv.w));
-                } else {
-                    float2 wt;
-                    if constexpr (CSR_LDS) wt = reinterpret_cast<const float2*>(s_w)[e];
-                    else wt = reinterpret_cast<const float2*>(wts)[e];
-                    gx = cfma(gx, wt, s_smp[an]);
+    auto flush = [&]() {
+        if (lane_on) {
+            const int kb = kpart * NK + kk;
+            int i = kb + N / 2;
+            if (i >= N) i -= N;
+            float* base = a.slots + ((int64_t)slot * a.C + c) * NPP * N * N;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                int j = q + Q * m + N / 2;
+                if (j >= N) j -= N;
+#pragma unroll
+                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + i] += acc[m][k];
+            }
+        }
+    };
+
+    for (int64_t f = f0; f < f1; ++f) {
+        if (v != cur_v) {
+            if (cur_v >= 0) flush();
+            cur_v = v;
+            c = v / KS;
+            kpart = v - c * KS;
+            slot = g - (int)(((int64_t)v * T) / L);
+            const ChanInfo ci = a.chans[c];
+            R = ci.R; W = ci.W; n_cell = ci.n_cell;
+            g_desc = a.cells_desc + ci.cell_off;
+            g_gant = a.grp_ant + ci.grp_off;
+            g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
+            __syncthreads();
+            if constexpr (PROG_LDS) {
+                for (int k = tid; k < ci.n_grp * GF4; k += THREADS) s_w[k] = g_w[k];
+                for (int k = tid; k < ci.n_grp; k += THREADS) s_gant[k] = g_gant[k];
+                for (int k = tid; k < n_cell; k += THREADS) s_desc[k] = g_desc[k];
+            }
+            // zero the window buffers: cells beyond W (and rows beyond R) up to
+            // the next multiple of 8 are read by the folds and must be zero
+            for (int k = tid; k < P * a.Rmax * a.WP; k += THREADS) s_G[k] = make_float2(0.f, 0.f);
+            for (int k = tid; k < P * a.Rmax * a.YP; k += THREADS) s_Y[k] = make_float2(0.f, 0.f);
+            nbR = (R + 7) >> 3;
+            nbW = (W + 7) >> 3;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int k = 0; k < NPP; ++k) acc[m][k] = 0.f;
+        }
+
+        // 1. decode the (t, c) row of A*P bytes; prefetch the next row
+        if (words) {
+#pragma unroll
+            for (int k = 0; k < kPrefetch; ++k) {
+                const int w = tid + k * THREADS;
+                if (w < nwords) {
+                    const uint32_t x = pre[k];
+                    s_smp[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
+                    s_smp[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
+                    s_smp[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
+                    s_smp[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
                 }
             }
-            s_G[r * a.WP + w] = gx;
-            if constexpr (P == 2) s_G[(a.Rmax + r) * a.WP + w] = gy;
+            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)t * a.C + c) * AP);
+            for (int w = tid + kPrefetch * THREADS; w < nwords; w += THREADS) {
+                const uint32_t x = row4[w];
+                s_smp[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
+                s_smp[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
+                s_smp[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
+                s_smp[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+            }
+        } else {
+            const uint8_t* row = a.samples + ((int64_t)t * a.C + c) * AP;
+            for (int k = tid; k < AP; k += THREADS) s_smp[k] = unpack44(row[k], a.nibble_order);
+        }
+        // advance to the next (channel, spectrum) and prefetch its row
+        if (++t == T) { t = 0; ++v; }
+        if (words && f + 1 < f1) prefetch(v, t);
+        __syncthreads();
+
+        // 2. gather gridding of the non-empty cells, both pols per cell
+        for (int k = tid; k < n_cell; k += THREADS) {
+            const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
+            const int off = (int)(d.x & 0xFFFFu);
+            const int ng = (int)(d.x >> 16);
+            float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
+            for (int j = 0; j < ng; ++j) {
+                const int gg = (int)d.y + j;
+                const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
+                const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
+                gather_group<P, REAL>(gx, gy, w, ia, s_smp);
+            }
+            s_G[off] = gx;
+            if constexpr (P == 2) s_G[a.Rmax * a.WP + off] = gy;
         }
         __syncthreads();
 
@@ -193,30 +299,29 @@ __global__ void __launch_bounds__(Shape<Q>::THREADS) fp32_kernel(Fp32Args a) {
             for (int rr = kk; rr < P * R; rr += NK) {
                 const int p = (P == 2 && rr >= R) ? 1 : 0;
                 const int r = rr - p * R;
-                float2 z[16];
-                fold_twiddle<Q>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, wq);
-                fft16(z);
+                float2 z[8];
+                fold_twiddle<N>(z, s_G + (p * a.Rmax + r) * a.WP, 1, nbW, tw, s_tw, q);
+                fft8(z);
                 float2* yrow = s_Y + (p * a.Rmax + r) * a.YP;
 #pragma unroll
-                for (int m = 0; m < 16; ++m) {
-                    if ((m / (16 / KS)) == kpart) yrow[q + Q * m - kpart * NK] = z[fft16_pos(m)];
-                }
+                for (int m = 0; m < 8; ++m)
+                    if ((m / (8 / KS)) == kpart) yrow[q + Q * m - kpart * NK] = z[fft8_pos(m)];
             }
         }
         __syncthreads();
 
         // 3b + 4. column pass per pol, products and accumulation in registers
         if (lane_on) {
-            float2 X[16];
-            fold_twiddle<Q>(X, s_Y + kk, a.YP, R, tw, wq);
-            fft16(X);
+            float2 X[8];
+            fold_twiddle<N>(X, s_Y + kk, a.YP, nbR, tw, s_tw, q);
+            fft8(X);
             if constexpr (P == 2) {
-                float2 Yv[16];
-                fold_twiddle<Q>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, R, tw, wq);
-                fft16(Yv);
+                float2 Yv[8];
+                fold_twiddle<N>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, nbR, tw, s_tw, q);
+                fft8(Yv);
 #pragma unroll
-                for (int m = 0; m < 16; ++m) {
-                    const float2 x = X[fft16_pos(m)], y = Yv[fft16_pos(m)];
+                for (int m = 0; m < 8; ++m) {
+                    const float2 x = X[fft8_pos(m)], y = Yv[fft8_pos(m)];
                     acc[m][0] = fmaf(x.x, x.x, fmaf(x.y, x.y, acc[m][0]));
                     acc[m][1] = fmaf(y.x, y.x, fmaf(y.y, y.y, acc[m][1]));
                     acc[m][2] = fmaf(x.x, y.x, fmaf(x.y, y.y, acc[m][2]));
@@ -224,42 +329,25 @@ __global__ void __launch_bounds__(Shape<Q>::THREADS) fp32_kernel(Fp32Args a) {
                 }
             } else {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) {
-                    const float2 x = X[fft16_pos(m)];
+                for (int m = 0; m < 8; ++m) {
+                    const float2 x = X[fft8_pos(m)];
                     acc[m][0] = fmaf(x.x, x.x, fmaf(x.y, x.y, acc[m][0]));
                 }
             }
         }
-        // the next iteration's first barrier orders these LDS reads before the
+        // the next iteration's decode barrier orders these LDS reads before the
         // next row pass overwrites s_Y
     }
-
-    // add this work item's sums into its slot; bin (k', j') -> pixel (k'+N/2, j'+N/2) mod N
-    if (lane_on) {
-        const int kb = kpart * NK + kk;
-        int i = kb + N / 2;
-        if (i >= N) i -= N;
-        float* base = a.slots + ((int64_t)s * a.C + c) * NPP * N * N;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            int j = q + Q * m + N / 2;
-            if (j >= N) j -= N;
-#pragma unroll
-            for (int k = 0; k < NPP; ++k) {
-                float* dst = base + ((int64_t)k * N + j) * N + i;
-                *dst += acc[m][k];
-            }
-        }
-    }
+    flush();
 }
 
 struct Layout {
-    uint32_t off_w, off_smp, off_G, off_Y, off_cp, off_ant;
+    uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
     size_t total;
-    int WP, YP;
+    int YP;
 };
 
-Layout layout(const SubDev& d, int KS, bool csr_lds) {
+Layout layout(const SubDev& d, int KS, bool prog_lds) {
     Layout L{};
     size_t b = 0;
     auto take = [&](size_t n) {
@@ -268,96 +356,124 @@ Layout layout(const SubDev& d, int KS, bool csr_lds) {
         b += n;
         return (uint32_t)o;
     };
-    L.WP = d.Wmax | 1;                 // odd row pitch (float2) against LDS bank conflicts
+    const int gf4 = d.real_taps ? (d.P == 2 ? 2 : 1) : (d.P == 2 ? 4 : 2);
     L.YP = d.N / KS + 1;
-    L.off_w = csr_lds ? take((size_t)d.Emax * 2 * d.P * sizeof(float)) : 0;
+    L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
+    L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
+    L.off_desc = prog_lds ? take((size_t)d.CellMax * 8) : 0;
     L.off_smp = take((size_t)d.A * d.P * sizeof(float2));
-    L.off_G = take((size_t)d.P * d.Rmax * L.WP * sizeof(float2));
+    L.off_G = take((size_t)d.P * d.Rmax * d.WP * sizeof(float2));
     L.off_Y = take((size_t)d.P * d.Rmax * L.YP * sizeof(float2));
-    L.off_cp = csr_lds ? take(((size_t)d.Rmax * d.Wmax + 1) * sizeof(uint32_t)) : 0;
-    L.off_ant = csr_lds ? take((size_t)d.Emax * sizeof(uint16_t)) : 0;
+    L.off_tw = take((size_t)d.N * sizeof(float2));
     L.total = (b + 15) & ~(size_t)15;
     return L;
 }
 
 using KernelFn = void (*)(Fp32Args);
 
-template <int Q, int P>
-KernelFn pick(bool csr) {
-    return csr ? fp32_kernel<Q, P, true> : fp32_kernel<Q, P, false>;
+template <int N, int P>
+KernelFn pick(bool real, bool prog) {
+    if (real) return prog ? fp32_kernel<N, P, true, true> : fp32_kernel<N, P, true, false>;
+    return prog ? fp32_kernel<N, P, false, true> : fp32_kernel<N, P, false, false>;
 }
 
-KernelFn select_kernel(int Q, int P, bool csr) {
-    switch (Q * 2 + (P - 1)) {
-#define EPIC_CASE(QQ)                             \
-    case QQ * 2 + 0: return pick<QQ, 1>(csr);     \
-    case QQ * 2 + 1: return pick<QQ, 2>(csr);
-        EPIC_CASE(1) EPIC_CASE(2) EPIC_CASE(3) EPIC_CASE(4) EPIC_CASE(5) EPIC_CASE(6) EPIC_CASE(7) EPIC_CASE(8)
+// Grid sizes with a kernel: multiples of 16 from 16 to 128.
+KernelFn select_kernel(int N, int P, bool real, bool prog) {
+    switch (N * 2 + (P - 1)) {
+#define EPIC_CASE(NN)                                   \
+    case NN * 2 + 0: return pick<NN, 1>(real, prog);    \
+    case NN * 2 + 1: return pick<NN, 2>(real, prog);
+        EPIC_CASE(16) EPIC_CASE(32) EPIC_CASE(48) EPIC_CASE(64) EPIC_CASE(80) EPIC_CASE(96) EPIC_CASE(112)
+        EPIC_CASE(128)
 #undef EPIC_CASE
     }
     return nullptr;
 }
 
-int threads_for(int Q) {
-    switch (Q) {
-        case 1: return Shape<1>::THREADS;
-        case 2: return Shape<2>::THREADS;
-        case 3: return Shape<3>::THREADS;
-        case 4: return Shape<4>::THREADS;
-        case 5: return Shape<5>::THREADS;
-        case 6: return Shape<6>::THREADS;
-        case 7: return Shape<7>::THREADS;
-        case 8: return Shape<8>::THREADS;
+int threads_for(int N) {
+    switch (N) {
+        case 16: return Shape<16>::THREADS;
+        case 32: return Shape<32>::THREADS;
+        case 48: return Shape<48>::THREADS;
+        case 64: return Shape<64>::THREADS;
+        case 80: return Shape<80>::THREADS;
+        case 96: return Shape<96>::THREADS;
+        case 112: return Shape<112>::THREADS;
+        case 128: return Shape<128>::THREADS;
     }
     return 0;
+}
+
+int ks_for(int N) {
+    switch (N) {
+        case 16: return Shape<16>::KS;
+        case 32: return Shape<32>::KS;
+        case 48: return Shape<48>::KS;
+        case 64: return Shape<64>::KS;
+        case 80: return Shape<80>::KS;
+        case 96: return Shape<96>::KS;
+        case 112: return Shape<112>::KS;
+        case 128: return Shape<128>::KS;
+    }
+    return 1;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
 }  // namespace
 
-// Choose the launch shape (pure host arithmetic).  The gather lists live in LDS
-// when they fit next to the per-spectrum buffers, else they stream from L2.
-// device < 0: no HIP calls (dry run).
-hipError_t fp32_configure(SubDev& d, int device) {
-    const int Q = d.N / 16;
-    if (Q < 1 || Q > 8 || d.N % 16 != 0) return hipErrorNotSupported;
-    d.KS = (Q >= 7) ? 2 : 1;
-    d.threads = threads_for(Q);
-    Layout with = layout(d, d.KS, true);
-    Layout without = layout(d, d.KS, false);
-    d.csr_in_lds = (with.total <= kLdsLimit / 2 || (with.total <= kLdsLimit && without.total > kLdsLimit / 2)) ? 1 : 0;
-    const Layout& L = d.csr_in_lds ? with : without;
+// Choose the launch shape.  The gather program lives in LDS when it fits next
+// to the per-spectrum buffers, else it streams from L2.  The grid is one
+// resident round of workgroups (occupancy x CUs).  device < 0: no HIP calls.
+hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
+    if (d.N < 16 || d.N > 128 || d.N % 16 != 0) return hipErrorNotSupported;
+    d.KS = ks_for(d.N);
+    d.threads = threads_for(d.N);
+    const Layout with = layout(d, d.KS, true);
+    const Layout without = layout(d, d.KS, false);
+    const bool prog = with.total <= kLdsLimit / 2 || (with.total <= kLdsLimit && without.total > kLdsLimit / 2);
+    const Layout& L = prog ? with : without;
     if (L.total > kLdsLimit) return hipErrorNotSupported;
     d.lds_bytes = L.total;
+    d.prog_lds = prog ? 1 : 0;
+    int occ = 2;
     if (device >= 0) {
-        KernelFn fn = select_kernel(Q, d.P, d.csr_in_lds != 0);
+        KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog);
         if (!fn) return hipErrorNotSupported;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
         if (e != hipSuccess) return e;
+        int blocks = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn), d.threads,
+                                                         L.total);
+        if (e != hipSuccess) return e;
+        occ = blocks > 0 ? blocks : 1;
     }
+    d.grid_wg = ((num_cu * occ + 7) / 8) * 8;
     return hipSuccess;
 }
 
 hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
-    const int Q = d.N / 16;
-    const Layout L = layout(d, d.KS, d.csr_in_lds != 0);
+    const bool prog = d.prog_lds != 0;
+    const Layout L = layout(d, d.KS, prog);
     Fp32Args a{};
     a.samples = samples;
     a.T = n_time;
     a.C = d.C; a.A = d.A; a.S = d.S;
-    a.chans = d.chans; a.cell_ptr = d.cell_ptr; a.ent_ant = d.ent_ant; a.ent_w = d.ent_w;
+    a.chans = d.chans;
+    a.cells_desc = d.cells_desc;
+    a.grp_ant = reinterpret_cast<const uint2*>(d.grp_ant);
+    a.grp_w = reinterpret_cast<const float4*>(d.grp_w);
     a.twiddle = d.twiddle; a.slots = d.slots;
-    a.Rmax = d.Rmax; a.WP = L.WP; a.YP = L.YP;
-    a.off_w = L.off_w; a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y;
-    a.off_cp = L.off_cp; a.off_ant = L.off_ant;
+    a.Rmax = d.Rmax; a.WP = d.WP; a.YP = L.YP;
+    a.off_w = L.off_w; a.off_gant = L.off_gant; a.off_desc = L.off_desc;
+    a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw;
     a.nibble_order = d.nibble_order;
-    a.units = d.C * d.S * d.KS;
-    a.units_per_xcd = (a.units + 7) / 8;
-    KernelFn fn = select_kernel(Q, d.P, d.csr_in_lds != 0);
+    a.grid_wg = d.grid_wg;
+    a.wg_per_xcd = (d.grid_wg + 7) / 8;
+    KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog);
     if (!fn) return hipErrorNotSupported;
-    hipLaunchKernelGGL(fn, dim3(8 * a.units_per_xcd), dim3(d.threads), L.total, st, a);
+    hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(d.threads), L.total, st, a);
     return hipGetLastError();
 }
 

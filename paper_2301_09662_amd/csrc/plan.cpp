@@ -32,9 +32,9 @@ struct SubHost {
     std::vector<int32_t> cells;      // [C][A][2]
     std::vector<double> gfrac;       // [C][A][2]
     std::vector<ChanInfo> chans;     // [C]
-    std::vector<uint32_t> cell_ptr;  // concatenated per channel
-    std::vector<uint16_t> ent_ant;
-    std::vector<uint8_t> ent_tap;
+    std::vector<CellDesc> cells_desc;
+    std::vector<uint16_t> grp_ant;
+    std::vector<uint8_t> grp_tap;
     SubDev dev{};
 };
 
@@ -102,17 +102,14 @@ epic_status geometry(SubHost& h) {
     return EPIC_OK;
 }
 
-// Per-channel aperture window and gather lists: for every window cell, the
-// (antenna, tap) pairs whose kernel footprint covers it, in antenna order.
+// Per-channel aperture window and gather program: for every non-empty window
+// cell, the (antenna, tap) pairs whose kernel footprint covers it, in antenna
+// order, padded to whole groups; cells sorted by group count (descending).
 void build_gather(SubHost& h) {
     const epic_array_desc& s = h.desc;
     const int A = s.n_ant, C = s.n_chan, K = s.kernel_k, hk = K / 2;
     h.chans.assign(C, ChanInfo{});
-    h.cell_ptr.clear();
-    h.ent_ant.clear();
-    h.ent_tap.clear();
-    int Rmax = 0, Wmax = 0, Emax = 0;
-    std::vector<uint32_t> count;
+    int Rmax = 0, Wmax = 0;
     for (int c = 0; c < C; ++c) {
         const int32_t* cc = &h.cells[(size_t)c * A * 2];
         int x0 = cc[0], x1 = cc[0], y0 = cc[1], y1 = cc[1];
@@ -120,37 +117,56 @@ void build_gather(SubHost& h) {
             x0 = std::min(x0, cc[2 * a]); x1 = std::max(x1, cc[2 * a]);
             y0 = std::min(y0, cc[2 * a + 1]); y1 = std::max(y1, cc[2 * a + 1]);
         }
-        x0 -= hk; y0 -= hk; x1 += hk; y1 += hk;
-        const int W = x1 - x0 + 1, R = y1 - y0 + 1, cellsN = R * W;
-        ChanInfo ci{};
-        ci.x0 = x0; ci.y0 = y0; ci.R = R; ci.W = W;
-        ci.cell_off = (int32_t)h.cell_ptr.size();
-        ci.ent_off = (int32_t)h.ent_ant.size();
-        ci.n_ent = A * K * K;
-        count.assign((size_t)cellsN + 1, 0u);
-        for (int a = 0; a < A; ++a)
-            for (int dy = -hk; dy <= hk; ++dy)
-                for (int dx = -hk; dx <= hk; ++dx) {
-                    int w = cc[2 * a] + dx - x0, r = cc[2 * a + 1] + dy - y0;
-                    count[(size_t)r * W + w + 1]++;
-                }
-        for (int k = 0; k < cellsN; ++k) count[k + 1] += count[k];
-        h.cell_ptr.insert(h.cell_ptr.end(), count.begin(), count.end());
-        std::vector<uint32_t> fill(count.begin(), count.end() - 1);
-        h.ent_ant.resize((size_t)ci.ent_off + ci.n_ent);
-        h.ent_tap.resize((size_t)ci.ent_off + ci.n_ent);
-        for (int a = 0; a < A; ++a)
-            for (int dy = -hk; dy <= hk; ++dy)
-                for (int dx = -hk; dx <= hk; ++dx) {
-                    int w = cc[2 * a] + dx - x0, r = cc[2 * a + 1] + dy - y0;
-                    uint32_t e = fill[(size_t)r * W + w]++;
-                    h.ent_ant[(size_t)ci.ent_off + e] = (uint16_t)a;
-                    h.ent_tap[(size_t)ci.ent_off + e] = (uint8_t)((dy + hk) * K + (dx + hk));
-                }
-        h.chans[c] = ci;
-        Rmax = std::max(Rmax, R); Wmax = std::max(Wmax, W); Emax = std::max(Emax, ci.n_ent);
+        ChanInfo& ci = h.chans[c];
+        ci.x0 = x0 - hk; ci.y0 = y0 - hk;
+        ci.W = x1 - x0 + 1 + 2 * hk; ci.R = y1 - y0 + 1 + 2 * hk;
+        Rmax = std::max(Rmax, ci.R); Wmax = std::max(Wmax, ci.W);
     }
-    h.dev.Rmax = Rmax; h.dev.Wmax = Wmax; h.dev.Emax = Emax;
+    // the transform folds read whole blocks of 8, so the LDS window holds
+    // zero-padded rows / columns up to the next multiple of 8
+    Rmax = (Rmax + 7) / 8 * 8;
+    Wmax = (Wmax + 7) / 8 * 8;
+    const int WP = Wmax | 1;   // odd LDS pitch against bank conflicts
+    h.dev.Rmax = Rmax; h.dev.Wmax = Wmax; h.dev.WP = WP;
+    h.cells_desc.clear(); h.grp_ant.clear(); h.grp_tap.clear();
+    int Gmax = 0, CellMax = 0;
+    std::vector<std::vector<std::pair<uint16_t, uint8_t>>> lists;
+    std::vector<int> order;
+    for (int c = 0; c < C; ++c) {
+        ChanInfo& ci = h.chans[c];
+        const int32_t* cc = &h.cells[(size_t)c * A * 2];
+        lists.assign((size_t)ci.R * ci.W, {});
+        for (int a = 0; a < A; ++a)
+            for (int dy = -hk; dy <= hk; ++dy)
+                for (int dx = -hk; dx <= hk; ++dx) {
+                    int w = cc[2 * a] + dx - ci.x0, r = cc[2 * a + 1] + dy - ci.y0;
+                    lists[(size_t)r * ci.W + w].push_back({(uint16_t)a, (uint8_t)((dy + hk) * K + (dx + hk))});
+                }
+        order.clear();
+        for (int k = 0; k < ci.R * ci.W; ++k)
+            if (!lists[k].empty()) order.push_back(k);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return lists[x].size() > lists[y].size(); });
+        ci.n_cell = (int32_t)order.size();
+        ci.cell_off = (int32_t)h.cells_desc.size();
+        ci.grp_off = (int32_t)(h.grp_ant.size() / kGroup);
+        uint32_t g = 0;
+        for (int k : order) {
+            const auto& L = lists[k];
+            const uint32_t ng = (uint32_t)((L.size() + kGroup - 1) / kGroup);
+            const uint32_t r = (uint32_t)(k / ci.W), w = (uint32_t)(k % ci.W);
+            h.cells_desc.push_back(CellDesc{(r * (uint32_t)WP + w) | (ng << 16), g});
+            for (uint32_t e = 0; e < ng * kGroup; ++e) {
+                if (e < L.size()) { h.grp_ant.push_back(L[e].first); h.grp_tap.push_back(L[e].second); }
+                else { h.grp_ant.push_back(0); h.grp_tap.push_back(255); }
+            }
+            g += ng;
+        }
+        ci.n_grp = (int32_t)g;
+        Gmax = std::max(Gmax, ci.n_grp);
+        CellMax = std::max(CellMax, ci.n_cell);
+    }
+    h.dev.Gmax = Gmax; h.dev.CellMax = CellMax;
 }
 
 epic_status hip_status(hipError_t e) {
@@ -188,14 +204,14 @@ void free_all(epic_plan_s* p) {
     p->allocations.clear();
 }
 
-// Time slots: enough independent (channel, slot) workgroups to fill the chip
-// a few times over, never more slots than spectra per call.
-int choose_slots(const SubDev& d, int num_cu, int64_t max_time, int n_sub) {
-    const int64_t target = 4LL * num_cu / std::max(1, n_sub) + 1;
-    int64_t per = (int64_t)d.C * d.KS;
-    int64_t S = (target + per - 1) / per;
-    S = std::max<int64_t>(1, std::min<int64_t>(S, 64));
-    S = std::min<int64_t>(S, max_time);
+// Slots per channel.  A launch runs grid_wg persistent workgroups, each taking
+// an equal contiguous run of the (channel, spectrum) sequence, so a channel is
+// split over at most ceil(grid_wg / channels) + 1 workgroups (and never more
+// than it has spectra); each piece adds into its own slot.
+int choose_slots(const SubDev& d, int64_t max_time) {
+    const int64_t V = (int64_t)d.C * d.KS;
+    int64_t S = (d.grid_wg + V - 1) / V + 1;
+    S = std::max<int64_t>(1, std::min<int64_t>(S, max_time));
     return (int)S;
 }
 
@@ -221,6 +237,9 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         SubDev& d = h.dev;
         d.A = h.desc.n_ant; d.P = h.desc.n_pol; d.C = h.desc.n_chan; d.N = h.desc.grid_n;
         d.K = h.desc.kernel_k; d.NPP = (d.P == 2) ? 4 : 1; d.nibble_order = h.desc.nibble_order;
+        d.real_taps = 1;
+        for (size_t k = 1; k < h.user_taps.size(); k += 2)
+            if (h.user_taps[k] != 0.0f) { d.real_taps = 0; break; }
     }
     if (!p->dry_run) {
         hipError_t e = hipSetDevice(p->device);
@@ -231,10 +250,10 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
     }
     for (SubHost& h : p->subs) {
         SubDev& d = h.dev;
-        hipError_t e = fp32_configure(d, p->dry_run ? -1 : p->device);
+        hipError_t e = fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
         if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
         if (e != hipSuccess) return hip_status(e);
-        d.S = choose_slots(d, p->num_cu, desc->max_time, desc->n_sub);
+        d.S = choose_slots(d, desc->max_time);
         // size checks (also in dry run)
         const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
         if (slot_bytes > 64.0 * (1ull << 30)) return EPIC_E_NOMEM;
@@ -242,8 +261,8 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
     if (p->dry_run) {
         for (SubHost& h : p->subs) {
             const SubDev& d = h.dev;
-            p->device_bytes += (int64_t)d.S * d.C * d.NPP * d.N * d.N * 4 + (int64_t)h.ent_ant.size() * (2 + 1 + 8 * d.P) +
-                               (int64_t)h.cell_ptr.size() * 4 + (int64_t)d.C * d.A * d.P * d.K * d.K * 8;
+            p->device_bytes += (int64_t)d.S * d.C * d.NPP * d.N * d.N * 4 + (int64_t)h.grp_ant.size() * (2 + 1 + 8 * d.P) +
+                               (int64_t)h.cells_desc.size() * 8 + (int64_t)d.C * d.A * d.P * d.K * d.K * 8;
         }
         return EPIC_OK;
     }
@@ -251,9 +270,9 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         SubDev& d = h.dev;
         epic_status s;
         if ((s = upload(p, &d.chans, h.chans, st)) != EPIC_OK) return s;
-        if ((s = upload(p, &d.cell_ptr, h.cell_ptr, st)) != EPIC_OK) return s;
-        if ((s = upload(p, &d.ent_ant, h.ent_ant, st)) != EPIC_OK) return s;
-        if ((s = upload(p, &d.ent_tap, h.ent_tap, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.cells_desc, h.cells_desc, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.grp_ant, h.grp_ant, st)) != EPIC_OK) return s;
+        if ((s = upload(p, &d.grp_tap, h.grp_tap, st)) != EPIC_OK) return s;
         if ((s = upload(p, &d.cells, h.cells, st)) != EPIC_OK) return s;
         if ((s = upload(p, &d.gfrac, h.gfrac, st)) != EPIC_OK) return s;
         const size_t ntap = (size_t)d.C * d.A * d.P * d.K * d.K * 2;
@@ -265,7 +284,7 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
                 return s;
         }
         d.gains = nullptr;
-        if ((s = dalloc(p, &d.ent_w, h.ent_ant.size() * 2 * (size_t)d.P)) != EPIC_OK) return s;
+        if ((s = dalloc(p, &d.grp_w, h.grp_ant.size() * 2 * (size_t)d.P)) != EPIC_OK) return s;
         if ((s = dalloc(p, &d.twiddle, (size_t)d.N)) != EPIC_OK) return s;
         const size_t nslot = (size_t)d.S * d.C * d.NPP * d.N * d.N;
         if ((s = dalloc(p, &d.slots, nslot)) != EPIC_OK) return s;
