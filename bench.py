@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cfg", type=int, default=2, help="workload config (default: station FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the FP16 matrix-core leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -86,35 +87,38 @@ def main():
     dev = torch.device("cuda", 0)
     host = [synth.samples(s, T) for s in subs]
     d_samples = [torch.from_numpy(x).to(dev) for x in host]
-    plan = E.epic_plan(subs, precision=wl.precision if args.cfg == 2 or wl.precision == "fp32" else "fp32",
-                       max_time=T)
-    info = E.epic_plan_query(plan)
-    outs = [torch.empty((s.n_chan, info["npp"][k], s.grid_n, s.grid_n), dtype=torch.float32, device=dev)
-            for k, s in enumerate(subs)]
     stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        E.epic_grid_fft_accumulate(plan, d_samples, T, stream)
-        if ev is not None:
-            ev[1].record(stream)
-        E.epic_readout(plan, outs, 1, stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    ms_per_step = wall / args.steps * 1e3
-
     samples_per_step = sum(s.n_ant * s.n_pol * s.n_chan * T for s in subs)
     flops_per_launch = sum(algorithmic_flops_per_ct(s) * s.n_chan * T for s in subs)
+
+    def run(precision, steps, warmup):
+        plan = E.epic_plan(subs, precision=precision, max_time=T)
+        info = E.epic_plan_query(plan)
+        outs = [torch.empty((s.n_chan, info["npp"][k], s.grid_n, s.grid_n), dtype=torch.float32, device=dev)
+                for k, s in enumerate(subs)]
+
+        def step(ev=None):
+            if ev is not None:
+                ev[0].record(stream)
+            E.epic_grid_fft_accumulate(plan, d_samples, T, stream)
+            if ev is not None:
+                ev[1].record(stream)
+            E.epic_readout(plan, outs, 1, stream)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        E.epic_destroy(plan)
+        return wall / steps * 1e3, kern_ms, [o.double().cpu().numpy() for o in outs], info
+
+    ms_per_step, kern_ms, img32, info32 = run("fp32", args.steps, args.warmup)
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
     res = {
         "metric": "imaged E-field samples/s (ant*chan*pol*t)",
@@ -137,7 +141,26 @@ def main():
                      "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch,
                      "frac_of_nonpacked_issue": achieved / FP32_NONPACKED_TFLOPS},
     }
-    E.epic_destroy(plan)
+    if not args.no_reduced:
+        ms16, kern16, img16, info16 = run("fp16", args.steps, args.warmup)
+        # error of the FP16 form per image against the FP32 result (all channels)
+        # and against the FP64 oracle (two sampled channels)
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from gpu_util import image_errors
+        errs = [image_errors(a, b)[0].max() for a, b in zip(img16, img32)]
+        red = {"precision": "fp16", "value": samples_per_step / (ms16 * 1e-3), "ms_per_step": ms16,
+               "kernel_ms": kern16, "speedup_vs_fp32": ms_per_step / ms16,
+               "max_rel_image_err_vs_fp32_all_channels": float(max(errs)),
+               "achieved_algorithmic_tflops": flops_per_launch / (kern16 * 1e-3) / 1e12}
+        if not args.no_cpu_baseline:
+            import oracle
+            e_or = []
+            for c in (0, subs[0].n_chan - 1):
+                ora = oracle.image(subs[0], host[0], chans=range(c, c + 1))
+                e_or.append(float(image_errors(img16[0][c:c + 1], ora[c:c + 1])[0].max()))
+            red["max_rel_image_err_vs_oracle_sampled"] = max(e_or)
+            red["oracle_sampled_channels"] = [0, subs[0].n_chan - 1]
+        res["reduced_precision"] = red
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(subs[0], host[0])
     print(json.dumps(res), flush=True)

@@ -22,6 +22,7 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-mcode-obj
              "-Wno-unused-command-line-argument"]
 SOURCES = [
     ("kernels_fp32.hip", []),
+    ("kernels_mfma.hip", []),
     ("kernels_aux.hip", []),
     ("plan.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

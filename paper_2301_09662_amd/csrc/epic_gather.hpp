@@ -1,0 +1,63 @@
+// Gridding helpers shared by the FP32 and matrix-core kernels: one group of
+// kGroup gather entries (antenna index + weight per pol) applied to the decoded
+// samples of one spectrum, and the group weight layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "epic_device.hpp"
+#include "epic_internal.hpp"
+
+namespace epic {
+
+// ---- gather gridding of one group of kGroup entries ------------------------
+template <int P, bool REAL>
+__device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float4* __restrict__ w,
+                                             const uint2 ia, const float2* __restrict__ smp) {
+    const int a[4] = {(int)(ia.x & 0xFFFFu), (int)(ia.x >> 16), (int)(ia.y & 0xFFFFu), (int)(ia.y >> 16)};
+    if constexpr (P == 2) {
+        const float4* s4 = reinterpret_cast<const float4*>(smp);
+        const float4 s0 = s4[a[0]], s1 = s4[a[1]], s2 = s4[a[2]], s3 = s4[a[3]];
+        if constexpr (REAL) {
+            const float4 w01 = w[0], w23 = w[1];   // (w0x, w0y, w1x, w1y), (w2x, w2y, w3x, w3y)
+            gx.x = fmaf(w01.x, s0.x, gx.x); gx.y = fmaf(w01.x, s0.y, gx.y);
+            gy.x = fmaf(w01.y, s0.z, gy.x); gy.y = fmaf(w01.y, s0.w, gy.y);
+            gx.x = fmaf(w01.z, s1.x, gx.x); gx.y = fmaf(w01.z, s1.y, gx.y);
+            gy.x = fmaf(w01.w, s1.z, gy.x); gy.y = fmaf(w01.w, s1.w, gy.y);
+            gx.x = fmaf(w23.x, s2.x, gx.x); gx.y = fmaf(w23.x, s2.y, gx.y);
+            gy.x = fmaf(w23.y, s2.z, gy.x); gy.y = fmaf(w23.y, s2.w, gy.y);
+            gx.x = fmaf(w23.z, s3.x, gx.x); gx.y = fmaf(w23.z, s3.y, gx.y);
+            gy.x = fmaf(w23.w, s3.z, gy.x); gy.y = fmaf(w23.w, s3.w, gy.y);
+        } else {
+            const float4 ww[4] = {w[0], w[1], w[2], w[3]};   // (wxr, wxi, wyr, wyi) per entry
+            const float4 ss[4] = {s0, s1, s2, s3};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                gx = cfma(gx, make_float2(ww[e].x, ww[e].y), make_float2(ss[e].x, ss[e].y));
+                gy = cfma(gy, make_float2(ww[e].z, ww[e].w), make_float2(ss[e].z, ss[e].w));
+            }
+        }
+    } else {
+        const float2 s0 = smp[a[0]], s1 = smp[a[1]], s2 = smp[a[2]], s3 = smp[a[3]];
+        if constexpr (REAL) {
+            const float4 ww = w[0];
+            gx.x = fmaf(ww.x, s0.x, gx.x); gx.y = fmaf(ww.x, s0.y, gx.y);
+            gx.x = fmaf(ww.y, s1.x, gx.x); gx.y = fmaf(ww.y, s1.y, gx.y);
+            gx.x = fmaf(ww.z, s2.x, gx.x); gx.y = fmaf(ww.z, s2.y, gx.y);
+            gx.x = fmaf(ww.w, s3.x, gx.x); gx.y = fmaf(ww.w, s3.y, gx.y);
+        } else {
+            const float4 w01 = w[0], w23 = w[1];
+            gx = cfma(gx, make_float2(w01.x, w01.y), s0);
+            gx = cfma(gx, make_float2(w01.z, w01.w), s1);
+            gx = cfma(gx, make_float2(w23.x, w23.y), s2);
+            gx = cfma(gx, make_float2(w23.z, w23.w), s3);
+        }
+    }
+}
+
+template <int P, bool REAL>
+constexpr int group_f4() {   // float4 words of weights per group
+    return REAL ? (P == 2 ? 2 : 1) : (P == 2 ? 4 : 2);
+}
+
+}  // namespace epic

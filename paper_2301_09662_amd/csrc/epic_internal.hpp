@@ -67,6 +67,10 @@ struct SubDev {
     int threads;
     size_t lds_bytes;
     int prog_lds;        // gather program copied to LDS (else read through L2)
+    // matrix-core (reduced precision) form
+    int precision;       // epic_precision of this sub-array's kernel
+    int KK;              // 32-deep MFMA steps per transform product
+    void* dft16;         // [2N][32 KK] FP16 real-form DFT matrix
 };
 
 // ---- launchers (defined in the .hip translation units) -----------------
@@ -80,6 +84,11 @@ hipError_t launch_entry_weights(const SubDev& d, hipStream_t st);
 // fp32_configure picks the launch shape; with device < 0 it makes no HIP call.
 hipError_t fp32_configure(SubDev& d, int device, int num_cu);
 hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
+
+// The FP16 matrix-core hot path (same contract as launch_fp32).
+hipError_t mfma_configure(SubDev& d, int device, int num_cu);
+hipError_t launch_dft_matrix(const SubDev& d, hipStream_t st);
+hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 
 // Ordered reduction of the slots into [C][NPP][N][N] (or Stokes), optional reset.
 hipError_t launch_readout(const SubDev& d, float* out, int stokes, int reset, hipStream_t st);

@@ -250,7 +250,9 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
     }
     for (SubHost& h : p->subs) {
         SubDev& d = h.dev;
-        hipError_t e = fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
+        d.precision = desc->precision;
+        hipError_t e = (d.precision == EPIC_FP32) ? fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu)
+                                                  : mfma_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
         if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
         if (e != hipSuccess) return hip_status(e);
         d.S = choose_slots(d, desc->max_time);
@@ -290,6 +292,12 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         if ((s = dalloc(p, &d.slots, nslot)) != EPIC_OK) return s;
         if ((s = hip_status(hipMemsetAsync(d.slots, 0, nslot * sizeof(float), st))) != EPIC_OK) return s;
         if ((s = hip_status(launch_twiddles(d, st))) != EPIC_OK) return s;
+        if (d.precision != EPIC_FP32) {
+            uint16_t* m = nullptr;
+            if ((s = dalloc(p, &m, (size_t)2 * d.N * 32 * d.KK)) != EPIC_OK) return s;
+            d.dft16 = m;
+            if ((s = hip_status(launch_dft_matrix(d, st))) != EPIC_OK) return s;
+        }
         if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
     }
     return hip_status(hipStreamSynchronize(st));
@@ -342,7 +350,7 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
         if (s != EPIC_OK) return s;
         if (desc->output == EPIC_OUT_STOKES && desc->sub[k].n_pol != 2) return EPIC_E_ARG;
     }
-    if (desc->precision != EPIC_FP32) return EPIC_E_UNSUPPORTED;
+    if (desc->precision == EPIC_FP8) return EPIC_E_UNSUPPORTED;
     if (desc->gridder != EPIC_GRID_AUTO && desc->gridder != EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
     if (desc->flags & (EPIC_F_REMOVE_AUTOCORR | EPIC_F_GRAPH | EPIC_F_AUTOTUNE)) return EPIC_E_UNSUPPORTED;
     epic_plan_s* p = new (std::nothrow) epic_plan_s();
@@ -376,7 +384,9 @@ epic_status epic_grid_fft_accumulate(epic_plan_t p, const uint8_t* const* d_samp
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
     for (size_t k = 0; k < p->subs.size(); ++k) {
-        hipError_t e = launch_fp32(p->subs[k].dev, d_samples[k], n_time, st);
+        const SubDev& d = p->subs[k].dev;
+        hipError_t e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
+                                                  : launch_mfma(d, d_samples[k], n_time, st);
         if (e != hipSuccess) return check_device(p, e);
     }
     return EPIC_OK;

@@ -1,0 +1,73 @@
+"""GPU parity of the FP16 matrix-core form against the FP64 oracle.
+
+Tolerance 1e-3 per image (relative Frobenius error and max |diff| over the
+channel peak), the bar for the reduced-precision forms.  The FP16 operands
+are the gridded aperture (4-bit samples times FP32 weights), the row-pass
+output and the DFT matrix; each adds ~2^-12 relative rounding, which a CPU
+simulation of the same arithmetic puts at ~1.2e-4 per image for the station
+layout, so 1e-3 leaves a margin of ~8.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_parity, image_errors, run_library
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2301_09662_amd import epic
+    return epic
+
+
+def test_station_subset(E):
+    sub = synth.shrink(synth.workload(3).subs[0], n_chan=5)
+    x = synth.samples(sub, 40)
+    (gpu,), info = run_library(E, [sub], [x], precision="fp16")
+    assert info["precision"] == E.EPIC_FP16
+    fro, mx = assert_parity(gpu, oracle.image(sub, x), TOL, "cfg3-subset")
+    print(f"fp16 station subset: max per-image rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+
+
+@pytest.mark.parametrize("cfg,k,nchan,T", [(4, 0, 2, 12), (4, 1, 3, 12), (4, 2, 2, 8), (5, 0, 1, 4), (1, 0, 4, 64)])
+def test_other_shapes(E, cfg, k, nchan, T):
+    """N = 64, 48, 96 (window 48 -> 3 MFMA steps), 128 (column split) and the
+    single-pol 32x32 case."""
+    sub = synth.shrink(synth.workload(cfg).subs[k], n_chan=nchan)
+    x = synth.samples(sub, T)
+    (gpu,), _ = run_library(E, [sub], [x], precision="fp16")
+    assert_parity(gpu, oracle.image(sub, x), TOL, f"fp16 cfg{cfg}.{k}")
+
+
+def test_split_calls_deterministic(E):
+    sub = synth.shrink(synth.workload(3).subs[0], n_chan=3)
+    x = synth.samples(sub, 21)
+    (a,), _ = run_library(E, [sub], [x], precision="fp16", calls=[21])
+    (b,), _ = run_library(E, [sub], [x], precision="fp16", calls=[21])
+    assert np.array_equal(a, b)
+    (c,), _ = run_library(E, [sub], [x], precision="fp16", calls=[10, 11])
+    assert_parity(c, oracle.image(sub, x), TOL, "fp16 split")
+
+
+def test_complex_user_taps(E):
+    sub = synth.shrink(synth.workload(3).subs[0], n_chan=2, n_ant=64)
+    x = synth.samples(sub, 12)
+    taps = np.random.default_rng(4).standard_normal((2, 64, 2, 3, 3, 2)).astype(np.float32)
+    (gpu,), _ = run_library(E, [sub], [x], precision="fp16", taps=[taps])
+    assert_parity(gpu, oracle.image(sub, x, taps=taps), TOL, "fp16 user taps")
+
+
+def test_full_station_sampled_channels(E):
+    """Config 3 at full size (132 channels, 1000 spectra in one call) against
+    the oracle on three channels; the per-channel error is reported."""
+    sub = synth.workload(3).subs[0]
+    x = synth.samples(sub, 1000)
+    (gpu,), _ = run_library(E, [sub], [x], precision="fp16")
+    for c in (0, 66, 131):
+        ora = oracle.image(sub, x, chans=range(c, c + 1))
+        fro, mx = assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"cfg3 full, channel {c}")
+        print(f"cfg3 channel {c}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
