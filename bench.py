@@ -72,7 +72,20 @@ def main():
     ap.add_argument("--cfg", type=int, default=2, help="workload config (default: station FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP16 matrix-core leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times) and exit: the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE hardware counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "repeats": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(channels shard across GPUs with no exchange; not built here)"}))

@@ -22,7 +22,8 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-mcode-obj
              "-Wno-unused-command-line-argument"]
 SOURCES = [
     ("kernels_fp32.hip", []),
-    ("kernels_mfma.hip", []),
+    # MFMA results in VGPRs: the products read them directly (no AGPR copies)
+    ("kernels_mfma.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form"]),
     ("kernels_aux.hip", []),
     ("plan.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

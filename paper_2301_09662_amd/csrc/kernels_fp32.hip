@@ -59,9 +59,13 @@ struct Shape {
     static constexpr int NK = N / KS;                          // columns per workgroup
     static constexpr int LANES = Q * NK;                       // (q, column) lanes
     static constexpr int THREADS = ((LANES + 63) / 64) * 64;
+    // register budget: two 8-wave workgroups per CU (<= 128 VGPRs); larger
+    // workgroups just have to fit once; smaller ones are left to the compiler
+    static constexpr int WAVES = THREADS / 64;
+    static constexpr int MIN_WAVES_PER_EU = WAVES == 8 ? 4 : (WAVES > 8 ? (WAVES + 3) / 4 : 1);
 };
 
-constexpr int kPrefetch = 4;   // sample words per thread held in registers ahead of use
+constexpr int kPrefetch = 1;   // sample words per thread held in registers ahead of use (more are loaded directly)
 
 // ---- DFT input fold ---------------------------------------------------------
 // z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * stride] * w_Q^{n2 q}.
@@ -90,7 +94,8 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
 }
 
 template <int N_, int P, bool REAL, bool PROG_LDS>
-__global__ void __launch_bounds__(Shape<N_>::THREADS) fp32_kernel(Fp32Args a) {
+__global__ void __launch_bounds__(Shape<N_>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(Shape<N_>::MIN_WAVES_PER_EU))) fp32_kernel(Fp32Args a) {
     using Sh = Shape<N_>;
     constexpr int N = Sh::N, Q = Sh::Q, KS = Sh::KS, NK = Sh::NK, LANES = Sh::LANES, THREADS = Sh::THREADS;
     constexpr int NPP = (P == 2) ? 4 : 1;
@@ -113,7 +118,8 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS) fp32_kernel(Fp32Args a) {
     float4* s_w = reinterpret_cast<float4*>(smem + a.off_w);
     uint2* s_gant = reinterpret_cast<uint2*>(smem + a.off_gant);
     uint2* s_desc = reinterpret_cast<uint2*>(smem + a.off_desc);
-    float2* s_smp = reinterpret_cast<float2*>(smem + a.off_smp);
+    float2* s_smp0 = reinterpret_cast<float2*>(smem + a.off_smp);   // two sample buffers
+    float2* s_smp1 = s_smp0 + a.A * P;
     float2* s_G = reinterpret_cast<float2*>(smem + a.off_G);
     float2* s_Y = reinterpret_cast<float2*>(smem + a.off_Y);
     float2* s_tw = reinterpret_cast<float2*>(smem + a.off_tw);
@@ -132,164 +138,179 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS) fp32_kernel(Fp32Args a) {
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.samples) & 3) == 0);
     const int nwords = AP >> 2;
 
-    float acc[8][NPP];
-    int v = (int)(f0 / T);
-    int64_t t = f0 - (int64_t)v * T;
-    int cur_v = -1, c = 0, kpart = 0, slot = 0, R = 0, W = 0, n_cell = 0, nbR = 0, nbW = 0;
-    const CellDesc* g_desc = nullptr;
-    const uint2* g_gant = nullptr;
-    const float4* g_w = nullptr;
-
-    uint32_t pre[kPrefetch];
+    uint32_t pre[kPrefetch];   // the next spectrum's sample words, loaded ahead of use
     auto prefetch = [&](int vv, int64_t tt) {
-        const int cc = vv / KS;
-        const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
+        const uint32_t* row4 =
+            reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + vv / KS) * AP);
 #pragma unroll
         for (int k = 0; k < kPrefetch; ++k) {
             const int w = tid + k * THREADS;
             pre[k] = (w < nwords) ? row4[w] : 0u;
         }
     };
-    if (words) prefetch(v, t);
 
-    auto flush = [&]() {
-        if (lane_on) {
-            const int kb = kpart * NK + kk;
-            int i = kb + N / 2;
-            if (i >= N) i -= N;
-            float* base = a.slots + ((int64_t)slot * a.C + c) * NPP * N * N;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                int j = q + Q * m + N / 2;
-                if (j >= N) j -= N;
-#pragma unroll
-                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + i] += acc[m][k];
-            }
-        }
-    };
-
-    for (int64_t f = f0; f < f1; ++f) {
-        if (v != cur_v) {
-            if (cur_v >= 0) flush();
-            cur_v = v;
-            c = v / KS;
-            kpart = v - c * KS;
-            slot = g - (int)(((int64_t)v * T) / L);
-            const ChanInfo ci = a.chans[c];
-            R = ci.R; W = ci.W; n_cell = ci.n_cell;
-            g_desc = a.cells_desc + ci.cell_off;
-            g_gant = a.grp_ant + ci.grp_off;
-            g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
-            __syncthreads();
-            if constexpr (PROG_LDS) {
-                for (int k = tid; k < ci.n_grp * GF4; k += THREADS) s_w[k] = g_w[k];
-                for (int k = tid; k < ci.n_grp; k += THREADS) s_gant[k] = g_gant[k];
-                for (int k = tid; k < n_cell; k += THREADS) s_desc[k] = g_desc[k];
-            }
-            // zero the window buffers: cells beyond W (and rows beyond R) up to
-            // the next multiple of 8 are read by the folds and must be zero
-            for (int k = tid; k < P * a.Rmax * a.WP; k += THREADS) s_G[k] = make_float2(0.f, 0.f);
-            for (int k = tid; k < P * a.Rmax * a.YP; k += THREADS) s_Y[k] = make_float2(0.f, 0.f);
-            nbR = (R + 7) >> 3;
-            nbW = (W + 7) >> 3;
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-#pragma unroll
-                for (int k = 0; k < NPP; ++k) acc[m][k] = 0.f;
-        }
-
-        // 1. decode the (t, c) row of A*P bytes; prefetch the next row
+    // decode one (t, c) row of A*P bytes into dst: the prefetched words first,
+    // any further words straight from memory
+    auto decode = [&](float2* dst, int cc, int64_t tt) {
         if (words) {
 #pragma unroll
             for (int k = 0; k < kPrefetch; ++k) {
                 const int w = tid + k * THREADS;
                 if (w < nwords) {
                     const uint32_t x = pre[k];
-                    s_smp[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                    s_smp[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                    s_smp[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                    s_smp[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                    dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
+                    dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
+                    dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
+                    dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
                 }
             }
-            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)t * a.C + c) * AP);
+            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
             for (int w = tid + kPrefetch * THREADS; w < nwords; w += THREADS) {
                 const uint32_t x = row4[w];
-                s_smp[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
+                dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
+                dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
+                dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
             }
         } else {
-            const uint8_t* row = a.samples + ((int64_t)t * a.C + c) * AP;
-            for (int k = tid; k < AP; k += THREADS) s_smp[k] = unpack44(row[k], a.nibble_order);
+            const uint8_t* row = a.samples + ((int64_t)tt * a.C + cc) * AP;
+            for (int k = tid; k < AP; k += THREADS) dst[k] = unpack44(row[k], a.nibble_order);
         }
-        // advance to the next (channel, spectrum) and prefetch its row
-        if (++t == T) { t = 0; ++v; }
-        if (words && f + 1 < f1) prefetch(v, t);
-        __syncthreads();
+    };
 
-        // 2. gather gridding of the non-empty cells, both pols per cell
-        for (int k = tid; k < n_cell; k += THREADS) {
-            const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
-            const int off = (int)(d.x & 0xFFFFu);
-            const int ng = (int)(d.x >> 16);
-            float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
-            for (int j = 0; j < ng; ++j) {
-                const int gg = (int)d.y + j;
-                const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
-                const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
-                gather_group<P, REAL>(gx, gy, w, ia, s_smp);
-            }
-            s_G[off] = gx;
-            if constexpr (P == 2) s_G[a.Rmax * a.WP + off] = gy;
+    int v = (int)(f0 / T);
+    int64_t t = f0 - (int64_t)v * T;
+    if (words) prefetch(v, t);
+    for (int64_t f = f0; f < f1;) {
+        // one channel segment: spectra t .. t+n-1 of virtual channel v
+        const int64_t n = (f1 - f < T - t) ? f1 - f : T - t;
+        const int c = v / KS;
+        const int kpart = v - c * KS;
+        const int slot = g - (int)(((int64_t)v * T) / L);
+        const ChanInfo ci = a.chans[c];
+        const int R = ci.R, W = ci.W, n_cell = ci.n_cell;
+        const int nbR = (R + 7) >> 3, nbW = (W + 7) >> 3;
+        const CellDesc* g_desc = a.cells_desc + ci.cell_off;
+        const uint2* g_gant = a.grp_ant + ci.grp_off;
+        const float4* g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
+        __syncthreads();   // the previous segment is done with every LDS buffer
+        if constexpr (PROG_LDS) {
+            for (int k = tid; k < ci.n_grp * GF4; k += THREADS) s_w[k] = g_w[k];
+            for (int k = tid; k < ci.n_grp; k += THREADS) s_gant[k] = g_gant[k];
+            for (int k = tid; k < n_cell; k += THREADS) s_desc[k] = g_desc[k];
         }
-        __syncthreads();
-
-        // 3a. row pass: R rows per pol, outputs for this workgroup's columns
-        if (lane_on) {
-            for (int rr = kk; rr < P * R; rr += NK) {
-                const int p = (P == 2 && rr >= R) ? 1 : 0;
-                const int r = rr - p * R;
-                float2 z[8];
-                fold_twiddle<N>(z, s_G + (p * a.Rmax + r) * a.WP, 1, nbW, tw, s_tw, q);
-                fft8(z);
-                float2* yrow = s_Y + (p * a.Rmax + r) * a.YP;
+        // zero the window buffers: cells beyond W (and rows beyond R) up to
+        // the next multiple of 8 are read by the folds and must be zero
+        for (int k = tid; k < P * a.Rmax * a.WP; k += THREADS) s_G[k] = make_float2(0.f, 0.f);
+        for (int k = tid; k < P * a.Rmax * a.YP; k += THREADS) s_Y[k] = make_float2(0.f, 0.f);
+        float acc[8][NPP];
 #pragma unroll
-                for (int m = 0; m < 8; ++m)
-                    if ((m / (8 / KS)) == kpart) yrow[q + Q * m - kpart * NK] = z[fft8_pos(m)];
-            }
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int k = 0; k < NPP; ++k) acc[m][k] = 0.f;
+
+        // decode the segment's first spectrum (the rest are decoded one step
+        // ahead, into the other sample buffer, while the current one is gridded)
+        decode(s_smp0, c, t);
+        if (words && f + 1 < f1) {
+            if (t + 1 < T) prefetch(v, t + 1);
+            else prefetch(v + 1, 0);
         }
         __syncthreads();
 
-        // 3b + 4. column pass per pol, products and accumulation in registers
-        if (lane_on) {
-            float2 X[8];
-            fold_twiddle<N>(X, s_Y + kk, a.YP, nbR, tw, s_tw, q);
-            fft8(X);
-            if constexpr (P == 2) {
-                float2 Yv[8];
-                fold_twiddle<N>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, nbR, tw, s_tw, q);
-                fft8(Yv);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const float2 x = X[fft8_pos(m)], y = Yv[fft8_pos(m)];
-                    acc[m][0] = fmaf(x.x, x.x, fmaf(x.y, x.y, acc[m][0]));
-                    acc[m][1] = fmaf(y.x, y.x, fmaf(y.y, y.y, acc[m][1]));
-                    acc[m][2] = fmaf(x.x, y.x, fmaf(x.y, y.y, acc[m][2]));
-                    acc[m][3] = fmaf(x.y, y.x, fmaf(-x.x, y.y, acc[m][3]));
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t tt = t + i;
+            float2* s_smp = (i & 1) ? s_smp1 : s_smp0;
+            float2* s_nxt = (i & 1) ? s_smp0 : s_smp1;
+
+            // 2. gather gridding of the non-empty cells, both pols per cell
+            for (int k = tid; k < n_cell; k += THREADS) {
+                const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
+                const int off = (int)(d.x & 0xFFFFu);
+                const int ng = (int)(d.x >> 16);
+                float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
+                for (int j = 0; j < ng; ++j) {
+                    const int gg = (int)d.y + j;
+                    const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
+                    const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
+                    gather_group<P, REAL>(gx, gy, w, ia, s_smp);
                 }
-            } else {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const float2 x = X[fft8_pos(m)];
-                    acc[m][0] = fmaf(x.x, x.x, fmaf(x.y, x.y, acc[m][0]));
+                s_G[off] = gx;
+                if constexpr (P == 2) s_G[a.Rmax * a.WP + off] = gy;
+            }
+            // 1'. decode the next spectrum of this segment into the other buffer
+            if (i + 1 < n) {
+                decode(s_nxt, c, tt + 1);
+                if (words && f + i + 2 < f1) {
+                    if (tt + 2 < T) prefetch(v, tt + 2);
+                    else prefetch(v + 1, 0);
                 }
             }
+            __syncthreads();
+
+            // 3a. row pass: R rows per pol, outputs for this workgroup's columns
+            if (lane_on) {
+                for (int rr = kk; rr < P * R; rr += NK) {
+                    const int p = (P == 2 && rr >= R) ? 1 : 0;
+                    const int r = rr - p * R;
+                    float2 z[8];
+                    fold_twiddle<N>(z, s_G + (p * a.Rmax + r) * a.WP, 1, nbW, tw, s_tw, q);
+                    fft8(z);
+                    float2* yrow = s_Y + (p * a.Rmax + r) * a.YP;
+#pragma unroll
+                    for (int m = 0; m < 8; ++m)
+                        if ((m / (8 / KS)) == kpart) yrow[q + Q * m - kpart * NK] = z[fft8_pos(m)];
+                }
+            }
+            __syncthreads();
+
+            // 3b + 4. column pass per pol, products and accumulation in registers
+            if (lane_on) {
+                float2 X[8];
+                fold_twiddle<N>(X, s_Y + kk, a.YP, nbR, tw, s_tw, q);
+                fft8(X);
+                if constexpr (P == 2) {
+                    float2 Yv[8];
+                    fold_twiddle<N>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, nbR, tw, s_tw, q);
+                    fft8(Yv);
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        const float2 x = X[fft8_pos(m)], y = Yv[fft8_pos(m)];
+                        acc[m][0] = fmaf(x.x, x.x, fmaf(x.y, x.y, acc[m][0]));
+                        acc[m][1] = fmaf(y.x, y.x, fmaf(y.y, y.y, acc[m][1]));
+                        acc[m][2] = fmaf(x.x, y.x, fmaf(x.y, y.y, acc[m][2]));
+                        acc[m][3] = fmaf(x.y, y.x, fmaf(-x.x, y.y, acc[m][3]));
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        const float2 x = X[fft8_pos(m)];
+                        acc[m][0] = fmaf(x.x, x.x, fmaf(x.y, x.y, acc[m][0]));
+                    }
+                }
+            }
+            // the next spectrum's decode barrier orders these LDS reads before
+            // the next row pass overwrites s_Y
         }
-        // the next iteration's decode barrier orders these LDS reads before the
-        // next row pass overwrites s_Y
+
+        // add the segment's sums into its slot; bin (k', j') -> pixel (+N/2 mod N)
+        if (lane_on) {
+            const int kb = kpart * NK + kk;
+            int ii = kb + N / 2;
+            if (ii >= N) ii -= N;
+            float* base = a.slots + ((int64_t)slot * a.C + c) * NPP * N * N;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                int j = q + Q * m + N / 2;
+                if (j >= N) j -= N;
+#pragma unroll
+                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + ii] += acc[m][k];
+            }
+        }
+        f += n;
+        ++v;
+        t = 0;
     }
-    flush();
 }
 
 struct Layout {
@@ -312,7 +333,7 @@ Layout layout(const SubDev& d, int KS, bool prog_lds) {
     L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
     L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
     L.off_desc = prog_lds ? take((size_t)d.CellMax * 8) : 0;
-    L.off_smp = take((size_t)d.A * d.P * sizeof(float2));
+    L.off_smp = take((size_t)2 * d.A * d.P * sizeof(float2));
     L.off_G = take((size_t)d.P * d.Rmax * d.WP * sizeof(float2));
     L.off_Y = take((size_t)d.P * d.Rmax * L.YP * sizeof(float2));
     L.off_tw = take((size_t)d.N * sizeof(float2));

@@ -102,7 +102,8 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
     float4* s_w = reinterpret_cast<float4*>(smem + a.off_w);
     uint2* s_gant = reinterpret_cast<uint2*>(smem + a.off_gant);
     uint2* s_desc = reinterpret_cast<uint2*>(smem + a.off_desc);
-    float2* s_smp = reinterpret_cast<float2*>(smem + a.off_smp);
+    float2* s_smp0 = reinterpret_cast<float2*>(smem + a.off_smp);   // two sample buffers
+    float2* s_smp1 = s_smp0 + a.A * P;
     _Float16* s_A1 = reinterpret_cast<_Float16*>(smem + a.off_A1);
     _Float16* s_B2 = reinterpret_cast<_Float16*>(smem + a.off_B2);
 
@@ -114,180 +115,222 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
         for (int ks = 0; ks < KK; ++ks)
             a2[h][ks] = *reinterpret_cast<const half8*>(a.dft + (size_t)(h * N + 16 * wave + l16) * K2 + 32 * ks +
                                                         8 * l4);
-    half8 b1[NT1][KK];   // row-pass operand for this wave's output tiles (depends on kpart)
 
     const int AP = a.A * P;
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.samples) & 3) == 0);
     const int nwords = AP >> 2;
 
-    float acc[IT][4][NPP];
+    constexpr int kPre = 1;   // sample words per thread loaded one spectrum ahead (more are loaded directly)
+    uint32_t pre[kPre];
+    auto prefetch = [&](int vv, int64_t tt) {
+        const uint32_t* row4 =
+            reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + vv / KS) * AP);
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int w = tid + k * THREADS;
+            pre[k] = (w < nwords) ? row4[w] : 0u;
+        }
+    };
+
+    // decode one (t, c) row of A*P bytes into dst: the prefetched words first,
+    // any further words straight from memory
+    auto decode = [&](float2* dst, int cc, int64_t tt) {
+        if (words) {
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) {
+                const int w = tid + k * THREADS;
+                if (w < nwords) {
+                    const uint32_t x = pre[k];
+                    dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
+                    dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
+                    dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
+                    dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                }
+            }
+            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
+            for (int w = tid + kPre * THREADS; w < nwords; w += THREADS) {
+                const uint32_t x = row4[w];
+                dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
+                dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
+                dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
+                dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+            }
+        } else {
+            const uint8_t* row = a.samples + ((int64_t)tt * a.C + cc) * AP;
+            for (int k = tid; k < AP; k += THREADS) dst[k] = unpack44(row[k], a.nibble_order);
+        }
+    };
+
     int v = (int)(f0 / T);
     int64_t t = f0 - (int64_t)v * T;
-    int cur_v = -1, c = 0, kpart = 0, slot = 0, n_cell = 0, R4 = 0, M1 = 0;
-    const CellDesc* g_desc = nullptr;
-    const uint2* g_gant = nullptr;
-    const float4* g_w = nullptr;
+    if (words) prefetch(v, t);
+    for (int64_t f = f0; f < f1;) {
+        // one channel segment: spectra t .. t+n-1 of virtual channel v
+        const int64_t n = (f1 - f < T - t) ? f1 - f : T - t;
+        const int c = v / KS;
+        const int kpart = v - c * KS;
+        const int slot = g - (int)(((int64_t)v * T) / L);
+        const ChanInfo ci = a.chans[c];
+        const int n_cell = ci.n_cell;
+        const int R4 = (ci.R + 3) & ~3;
+        const int M1 = P * R4;
+        const CellDesc* g_desc = a.cells_desc + ci.cell_off;
+        const uint2* g_gant = a.grp_ant + ci.grp_off;
+        const float4* g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
+        half8 b1[NT1][KK];   // row-pass operand for this wave's output tiles
+#pragma unroll
+        for (int u = 0; u < NT1; ++u) {
+            const int nloc = 16 * (wave * NT1 + u) + l16;          // own-column index in [0, 2 NK)
+            const int row = (nloc < NK) ? kpart * NK + nloc : N + kpart * NK + (nloc - NK);
+#pragma unroll
+            for (int ks = 0; ks < KK; ++ks)
+                b1[u][ks] = *reinterpret_cast<const half8*>(a.dft + (size_t)row * K2 + 32 * ks + 8 * l4);
+        }
+        __syncthreads();   // the previous segment is done with every LDS buffer
+        if constexpr (PROG_LDS) {
+            for (int k = tid; k < ci.n_grp * GF4; k += THREADS) s_w[k] = g_w[k];
+            for (int k = tid; k < ci.n_grp; k += THREADS) s_gant[k] = g_gant[k];
+            for (int k = tid; k < n_cell; k += THREADS) s_desc[k] = g_desc[k];
+        }
+        // zero both operand buffers: cells outside the window, rows beyond R
+        // and the padding up to whole MFMA steps are never written again
+        {
+            uint4* z1 = reinterpret_cast<uint4*>(s_A1);
+            for (int k = tid; k < a.M1max * A1P / 8; k += THREADS) z1[k] = make_uint4(0, 0, 0, 0);
+            uint4* z2 = reinterpret_cast<uint4*>(s_B2);
+            for (int k = tid; k < P * NK * B2P / 8; k += THREADS) z2[k] = make_uint4(0, 0, 0, 0);
+        }
+        float acc[IT][4][NPP];
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int k = 0; k < NPP; ++k) acc[it][e][k] = 0.f;
 
-    auto flush = [&]() {
+        // decode the segment's first spectrum (the rest are decoded one step
+        // ahead, into the other sample buffer, while the current one is gridded)
+        decode(s_smp0, c, t);
+        if (words && f + 1 < f1) {
+            if (t + 1 < T) prefetch(v, t + 1);
+            else prefetch(v + 1, 0);
+        }
+        __syncthreads();
+
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t tt = t + i;
+            float2* s_smp = (i & 1) ? s_smp1 : s_smp0;
+            float2* s_nxt = (i & 1) ? s_smp0 : s_smp1;
+
+            // 2. gather gridding (FP32), stored as the FP16 row-pass operand:
+            //    row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)]
+            for (int k = tid; k < n_cell; k += THREADS) {
+                const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
+                const int off = (int)(d.x & 0xFFFFu);
+                const int ng = (int)(d.x >> 16);
+                float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
+                for (int j = 0; j < ng; ++j) {
+                    const int gg = (int)d.y + j;
+                    const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
+                    const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
+                    gather_group<P, REAL>(gx, gy, w, ia, s_smp);
+                }
+                const int r = off / a.WP, w = off - r * a.WP;
+                _Float16* dst = s_A1 + r * A1P + w;
+                dst[0] = (_Float16)gx.x;
+                dst[KPAD] = (_Float16)gx.y;
+                if constexpr (P == 2) {
+                    dst[R4 * A1P] = (_Float16)gy.x;
+                    dst[R4 * A1P + KPAD] = (_Float16)gy.y;
+                }
+            }
+            // 1'. decode the next spectrum of this segment into the other buffer
+            if (i + 1 < n) {
+                decode(s_nxt, c, tt + 1);
+                if (words && f + i + 2 < f1) {
+                    if (tt + 2 < T) prefetch(v, tt + 2);
+                    else prefetch(v + 1, 0);
+                }
+            }
+            __syncthreads();
+
+            // 3a. row pass: [M1 x K2] x [K2 x 2 NK] on the matrix cores; each wave
+            //     takes NT1 output tiles and writes them, rounded to FP16, as the
+            //     column-pass operand B2[p][i][Re Y(0..) | Im Y(0..)]
+            for (int mt = 0; mt < (M1 + 15) / 16; ++mt) {
+                half8 af[KK];
+#pragma unroll
+                for (int ks = 0; ks < KK; ++ks)
+                    af[ks] = *reinterpret_cast<const half8*>(s_A1 + (16 * mt + l16) * A1P + 32 * ks + 8 * l4);
+                const int m0 = 16 * mt + 4 * l4;
+#pragma unroll
+                for (int u = 0; u < NT1; ++u) {
+                    floatx4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < KK; ++ks) d = mfma16(af[ks], b1[u][ks], d);
+                    if (m0 < M1) {
+                        const int p = (P == 2 && m0 >= R4) ? 1 : 0;
+                        const int r0 = m0 - p * R4;
+                        const int nloc = 16 * (wave * NT1 + u) + l16;
+                        const int part = nloc >= NK ? 1 : 0;
+                        const int iloc = nloc - part * NK;
+                        half4 hv;
+                        hv[0] = (_Float16)d[0]; hv[1] = (_Float16)d[1]; hv[2] = (_Float16)d[2]; hv[3] = (_Float16)d[3];
+                        *reinterpret_cast<half4*>(s_B2 + (p * NK + iloc) * B2P + part * KPAD + r0) = hv;
+                    }
+                }
+            }
+            __syncthreads();
+
+            // 3b + 4. column pass: E~ rows 16w.. for every own column tile, both
+            //         pols, then the products of Eq. 5 accumulated in registers
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                floatx4 er[P], ei[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    er[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    ei[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < KK; ++ks) {
+                        const half8 bf = *reinterpret_cast<const half8*>(s_B2 + (p * NK + 16 * it + l16) * B2P +
+                                                                         32 * ks + 8 * l4);
+                        er[p] = mfma16(a2[0][ks], bf, er[p]);
+                        ei[p] = mfma16(a2[1][ks], bf, ei[p]);
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float xr = er[0][e], xi = ei[0][e];
+                    acc[it][e][0] = fmaf(xr, xr, fmaf(xi, xi, acc[it][e][0]));
+                    if constexpr (P == 2) {
+                        const float yr = er[1][e], yi = ei[1][e];
+                        acc[it][e][1] = fmaf(yr, yr, fmaf(yi, yi, acc[it][e][1]));
+                        acc[it][e][2] = fmaf(xr, yr, fmaf(xi, yi, acc[it][e][2]));
+                        acc[it][e][3] = fmaf(xi, yr, fmaf(-xr, yi, acc[it][e][3]));
+                    }
+                }
+            }
+        }
+
+        // add the segment's sums into its slot; bin -> pixel (+N/2 mod N)
         float* base = a.slots + ((int64_t)slot * a.C + c) * NPP * N * N;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
-            int i = kpart * NK + 16 * it + l16 + N / 2;
-            if (i >= N) i -= N;
+            int ii = kpart * NK + 16 * it + l16 + N / 2;
+            if (ii >= N) ii -= N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 int j = 16 * wave + 4 * l4 + e + N / 2;
                 if (j >= N) j -= N;
 #pragma unroll
-                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + i] += acc[it][e][k];
+                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + ii] += acc[it][e][k];
             }
         }
-    };
-
-    for (int64_t f = f0; f < f1; ++f) {
-        if (v != cur_v) {
-            if (cur_v >= 0) flush();
-            cur_v = v;
-            c = v / KS;
-            kpart = v - c * KS;
-            slot = g - (int)(((int64_t)v * T) / L);
-            const ChanInfo ci = a.chans[c];
-            n_cell = ci.n_cell;
-            R4 = (ci.R + 3) & ~3;
-            M1 = P * R4;
-            g_desc = a.cells_desc + ci.cell_off;
-            g_gant = a.grp_ant + ci.grp_off;
-            g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
-#pragma unroll
-            for (int u = 0; u < NT1; ++u) {
-                const int nloc = 16 * (wave * NT1 + u) + l16;          // own-column index in [0, 2 NK)
-                const int row = (nloc < NK) ? kpart * NK + nloc : N + kpart * NK + (nloc - NK);
-#pragma unroll
-                for (int ks = 0; ks < KK; ++ks)
-                    b1[u][ks] = *reinterpret_cast<const half8*>(a.dft + (size_t)row * K2 + 32 * ks + 8 * l4);
-            }
-            __syncthreads();
-            if constexpr (PROG_LDS) {
-                for (int k = tid; k < ci.n_grp * GF4; k += THREADS) s_w[k] = g_w[k];
-                for (int k = tid; k < ci.n_grp; k += THREADS) s_gant[k] = g_gant[k];
-                for (int k = tid; k < n_cell; k += THREADS) s_desc[k] = g_desc[k];
-            }
-            // zero both operand buffers: cells outside the window, rows beyond R
-            // and the padding up to whole MFMA steps are never written again
-            {
-                uint4* z1 = reinterpret_cast<uint4*>(s_A1);
-                for (int k = tid; k < a.M1max * A1P / 8; k += THREADS) z1[k] = make_uint4(0, 0, 0, 0);
-                uint4* z2 = reinterpret_cast<uint4*>(s_B2);
-                for (int k = tid; k < P * NK * B2P / 8; k += THREADS) z2[k] = make_uint4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int it = 0; it < IT; ++it)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int k = 0; k < NPP; ++k) acc[it][e][k] = 0.f;
-        }
-
-        // 1. decode the (t, c) row into LDS
-        if (words) {
-            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)t * a.C + c) * AP);
-            for (int w = tid; w < nwords; w += THREADS) {
-                const uint32_t x = row4[w];
-                s_smp[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                s_smp[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
-            }
-        } else {
-            const uint8_t* row = a.samples + ((int64_t)t * a.C + c) * AP;
-            for (int k = tid; k < AP; k += THREADS) s_smp[k] = unpack44(row[k], a.nibble_order);
-        }
-        if (++t == T) { t = 0; ++v; }
-        __syncthreads();
-
-        // 2. gather gridding (FP32), stored as the FP16 row-pass operand:
-        //    row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)]
-        for (int k = tid; k < n_cell; k += THREADS) {
-            const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
-            const int off = (int)(d.x & 0xFFFFu);
-            const int ng = (int)(d.x >> 16);
-            float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
-            for (int j = 0; j < ng; ++j) {
-                const int gg = (int)d.y + j;
-                const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
-                const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
-                gather_group<P, REAL>(gx, gy, w, ia, s_smp);
-            }
-            const int r = off / a.WP, w = off - r * a.WP;
-            _Float16* dst = s_A1 + r * A1P + w;
-            dst[0] = (_Float16)gx.x;
-            dst[KPAD] = (_Float16)gx.y;
-            if constexpr (P == 2) {
-                dst[R4 * A1P] = (_Float16)gy.x;
-                dst[R4 * A1P + KPAD] = (_Float16)gy.y;
-            }
-        }
-        __syncthreads();
-
-        // 3a. row pass: [M1 x K2] x [K2 x 2 NK] on the matrix cores; each wave
-        //     takes NT1 output tiles and writes them, rounded to FP16, as the
-        //     column-pass operand B2[p][i][Re Y(0..) | Im Y(0..)]
-        for (int mt = 0; mt < (M1 + 15) / 16; ++mt) {
-            half8 af[KK];
-#pragma unroll
-            for (int ks = 0; ks < KK; ++ks)
-                af[ks] = *reinterpret_cast<const half8*>(s_A1 + (16 * mt + l16) * A1P + 32 * ks + 8 * l4);
-            const int m0 = 16 * mt + 4 * l4;
-#pragma unroll
-            for (int u = 0; u < NT1; ++u) {
-                floatx4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int ks = 0; ks < KK; ++ks) d = mfma16(af[ks], b1[u][ks], d);
-                if (m0 < M1) {
-                    const int p = (P == 2 && m0 >= R4) ? 1 : 0;
-                    const int r0 = m0 - p * R4;
-                    const int nloc = 16 * (wave * NT1 + u) + l16;
-                    const int part = nloc >= NK ? 1 : 0;
-                    const int iloc = nloc - part * NK;
-                    half4 hv;
-                    hv[0] = (_Float16)d[0]; hv[1] = (_Float16)d[1]; hv[2] = (_Float16)d[2]; hv[3] = (_Float16)d[3];
-                    *reinterpret_cast<half4*>(s_B2 + (p * NK + iloc) * B2P + part * KPAD + r0) = hv;
-                }
-            }
-        }
-        __syncthreads();
-
-        // 3b + 4. column pass: E~ rows 16w.. for every own column tile, both
-        //         pols, then the products of Eq. 5 accumulated in registers
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            floatx4 er[P], ei[P];
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                er[p] = floatx4{0.f, 0.f, 0.f, 0.f};
-                ei[p] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int ks = 0; ks < KK; ++ks) {
-                    const half8 bf = *reinterpret_cast<const half8*>(s_B2 + (p * NK + 16 * it + l16) * B2P + 32 * ks +
-                                                                     8 * l4);
-                    er[p] = mfma16(a2[0][ks], bf, er[p]);
-                    ei[p] = mfma16(a2[1][ks], bf, ei[p]);
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float xr = er[0][e], xi = ei[0][e];
-                acc[it][e][0] = fmaf(xr, xr, fmaf(xi, xi, acc[it][e][0]));
-                if constexpr (P == 2) {
-                    const float yr = er[1][e], yi = ei[1][e];
-                    acc[it][e][1] = fmaf(yr, yr, fmaf(yi, yi, acc[it][e][1]));
-                    acc[it][e][2] = fmaf(xr, yr, fmaf(xi, yi, acc[it][e][2]));
-                    acc[it][e][3] = fmaf(xi, yr, fmaf(-xr, yi, acc[it][e][3]));
-                }
-            }
-        }
+        f += n;
+        ++v;
+        t = 0;
     }
-    flush();
 }
 
 // ---- launch shapes -----------------------------------------------------------
@@ -316,7 +359,7 @@ Layout layout(const SubDev& d, bool prog_lds) {
     L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
     L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
     L.off_desc = prog_lds ? take((size_t)d.CellMax * 8) : 0;
-    L.off_smp = take((size_t)d.A * d.P * sizeof(float2));
+    L.off_smp = take((size_t)2 * d.A * d.P * sizeof(float2));
     L.off_A1 = take((size_t)L.M1max * (K2 + 8) * 2);
     L.off_B2 = take((size_t)d.P * NK * (K2 + 8) * 2);
     L.total = (b + 15) & ~(size_t)15;
