@@ -133,7 +133,11 @@ typedef struct {
     int64_t device_bytes;          /* device memory owned by the plan */
     int64_t lds_bytes[16];         /* LDS per workgroup of each sub-array's kernel */
     int32_t graph;                 /* 1 if accumulate replays a hipGraph */
-    int32_t autotuned;             /* 1 if launch shapes came from timing */
+    int32_t autotuned;             /* 1 if the work split came from timing */
+    int32_t batched;               /* 1 if all sub-arrays run in one launch */
+    int32_t weight[16];            /* batched: cost of one spectrum per sub-array */
+    int32_t col_split[16];         /* KS: workgroups sharing one spectrum's image columns */
+    int32_t workgroups[16];        /* persistent workgroups of the sub-array's launch */
 } epic_plan_info;
 
 /*
@@ -201,6 +205,19 @@ epic_status epic_plan_query(epic_plan_t plan, epic_plan_info* info);
  * dry-run plans.  EPIC_E_ARG on bad arguments.
  */
 epic_status epic_debug_geometry(epic_plan_t plan, int32_t sub, int32_t* h_cells);
+
+/*
+ * epic_debug_schedule -- the work split of one accumulate call of n_time
+ * spectra, computed on the host with the same functions the kernels use.
+ * For sub-array `sub` and every spectrum index k = v * n_time + t (virtual
+ * channel v = c * KS + column part, KS = col_split from epic_plan_query) it
+ * writes the owning workgroup to h_wg[k] and the partial-accumulator slot
+ * that workgroup adds it into to h_slot[k]; both arrays hold
+ * n_chan * KS * n_time int32 values.  Works on dry-run plans.  EPIC_E_ARG on
+ * bad arguments or n_time outside [1, max_time]; EPIC_E_STATE if the split
+ * gives a spectrum two owners or none, or a slot outside [0, slots).
+ */
+epic_status epic_debug_schedule(epic_plan_t plan, int32_t sub, int64_t n_time, int32_t* h_wg, int32_t* h_slot);
 
 /*
  * epic_debug_unpack -- run the device 4+4-bit decoder of the hot path on n

@@ -67,10 +67,33 @@ struct SubDev {
     int threads;
     size_t lds_bytes;
     int prog_lds;        // gather program copied to LDS (else read through L2)
+    int smp_bufs = 2;    // FP32: decoded sample buffers (2: decode overlaps gridding)
     // matrix-core (reduced precision) form
     int precision;       // epic_precision of this sub-array's kernel
     int KK;              // 32-deep MFMA steps per transform product
     void* dft16;         // [2N][32 KK] FP16 real-form DFT matrix
+};
+
+// One sub-array as seen by the batched (several sub-arrays in one launch)
+// matrix-core kernel; a device copy of the table is passed to the kernel.
+struct BatchSub {
+    const ChanInfo* chans;
+    const CellDesc* cells_desc;
+    const uint16_t* grp_ant;
+    const float* grp_w;
+    const uint16_t* dft;      // FP16 real-form DFT matrix [2N][32 KK]
+    float* slots;             // [S][C][NPP][N][N]
+    int C, A, V;              // channels, antennas, virtual channels (C * KS)
+    int N, KK, KS, NK, IT, WAVES, NT1, WP, M1max;
+    int nibble_order, S, weight, prog_lds;
+};
+
+// Launch state of a batched plan.
+struct BatchDev {
+    BatchSub* table;          // device [n_sub]
+    int grid_wg, threads, kkmax, P, real, prog_lds, smp_stride;
+    size_t lds_bytes;
+    uint32_t off[6];
 };
 
 // ---- launchers (defined in the .hip translation units) -----------------
@@ -89,6 +112,12 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
 hipError_t mfma_configure(SubDev& d, int device, int num_cu);
 hipError_t launch_dft_matrix(const SubDev& d, hipStream_t st);
 hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
+
+// Several FP16 sub-arrays in one persistent launch.
+hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, int num_cu);
+BatchSub batch_entry(const SubDev& d, int weight);
+hipError_t launch_batch(const BatchDev& bd, const uint8_t* const* samples, int n_sub, int64_t n_time,
+                        hipStream_t st);
 
 // Ordered reduction of the slots into [C][NPP][N][N] (or Stokes), optional reset.
 hipError_t launch_readout(const SubDev& d, float* out, int stokes, int reset, hipStream_t st);

@@ -30,6 +30,7 @@
 #include "epic_device.hpp"
 #include "epic_gather.hpp"
 #include "epic_internal.hpp"
+#include "epic_sched.hpp"
 
 namespace epic {
 
@@ -48,6 +49,7 @@ struct Fp32Args {
     int Rmax, WP, YP;
     uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
     int nibble_order;
+    int dbuf;                 // 1: two sample buffers (decode overlaps gridding)
     int grid_wg, wg_per_xcd;
 };
 
@@ -110,16 +112,16 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     const int64_t T = a.T;
     const int64_t total = (int64_t)a.C * KS * T;
     const int64_t L = (total + a.grid_wg - 1) / a.grid_wg;
-    const int64_t f0 = (int64_t)g * L;
-    const int64_t f1 = (f0 + L < total) ? f0 + L : total;
+    int64_t f0, f1;
+    owned_range(g, L, 0, 1, total, &f0, &f1);
     if (f0 >= f1) return;
 
     extern __shared__ __align__(16) unsigned char smem[];
     float4* s_w = reinterpret_cast<float4*>(smem + a.off_w);
     uint2* s_gant = reinterpret_cast<uint2*>(smem + a.off_gant);
     uint2* s_desc = reinterpret_cast<uint2*>(smem + a.off_desc);
-    float2* s_smp0 = reinterpret_cast<float2*>(smem + a.off_smp);   // two sample buffers
-    float2* s_smp1 = s_smp0 + a.A * P;
+    float2* s_smp0 = reinterpret_cast<float2*>(smem + a.off_smp);   // one or two sample buffers
+    float2* s_smp1 = a.dbuf ? s_smp0 + a.A * P : s_smp0;
     float2* s_G = reinterpret_cast<float2*>(smem + a.off_G);
     float2* s_Y = reinterpret_cast<float2*>(smem + a.off_Y);
     float2* s_tw = reinterpret_cast<float2*>(smem + a.off_tw);
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         const int64_t n = (f1 - f < T - t) ? f1 - f : T - t;
         const int c = v / KS;
         const int kpart = v - c * KS;
-        const int slot = g - (int)(((int64_t)v * T) / L);
+        const int slot = slot_of(g, v, t, T, 0, 1, L);
         const ChanInfo ci = a.chans[c];
         const int R = ci.R, W = ci.W, n_cell = ci.n_cell;
         const int nbR = (R + 7) >> 3, nbW = (W + 7) >> 3;
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 if constexpr (P == 2) s_G[a.Rmax * a.WP + off] = gy;
             }
             // 1'. decode the next spectrum of this segment into the other buffer
-            if (i + 1 < n) {
+            if (a.dbuf && i + 1 < n) {
                 decode(s_nxt, c, tt + 1);
                 if (words && f + i + 2 < f1) {
                     if (tt + 2 < T) prefetch(v, tt + 2);
@@ -263,6 +265,16 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 }
             }
             __syncthreads();
+
+            // 1'. with one sample buffer the next spectrum is decoded here, after
+            //     every gather read of the current one
+            if (!a.dbuf && i + 1 < n) {
+                decode(s_nxt, c, tt + 1);
+                if (words && f + i + 2 < f1) {
+                    if (tt + 2 < T) prefetch(v, tt + 2);
+                    else prefetch(v + 1, 0);
+                }
+            }
 
             // 3b + 4. column pass per pol, products and accumulation in registers
             if (lane_on) {
@@ -290,7 +302,9 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 }
             }
             // the next spectrum's decode barrier orders these LDS reads before
-            // the next row pass overwrites s_Y
+            // the next row pass overwrites s_Y; with one sample buffer this one
+            // orders the decode above before the next gather
+            if (!a.dbuf) __syncthreads();
         }
 
         // add the segment's sums into its slot; bin (k', j') -> pixel (+N/2 mod N)
@@ -319,7 +333,7 @@ struct Layout {
     int YP;
 };
 
-Layout layout(const SubDev& d, int KS, bool prog_lds) {
+Layout layout(const SubDev& d, int KS, bool prog_lds, int bufs) {
     Layout L{};
     size_t b = 0;
     auto take = [&](size_t n) {
@@ -333,7 +347,7 @@ Layout layout(const SubDev& d, int KS, bool prog_lds) {
     L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
     L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
     L.off_desc = prog_lds ? take((size_t)d.CellMax * 8) : 0;
-    L.off_smp = take((size_t)2 * d.A * d.P * sizeof(float2));
+    L.off_smp = take((size_t)bufs * d.A * d.P * sizeof(float2));
     L.off_G = take((size_t)d.P * d.Rmax * d.WP * sizeof(float2));
     L.off_Y = take((size_t)d.P * d.Rmax * L.YP * sizeof(float2));
     L.off_tw = take((size_t)d.N * sizeof(float2));
@@ -401,8 +415,10 @@ hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
     if (d.N < 16 || d.N > 128 || d.N % 16 != 0) return hipErrorNotSupported;
     d.KS = ks_for(d.N);
     d.threads = threads_for(d.N);
-    const Layout with = layout(d, d.KS, true);
-    const Layout without = layout(d, d.KS, false);
+    // two sample buffers unless only one fits
+    d.smp_bufs = layout(d, d.KS, false, 2).total <= kLdsLimit ? 2 : 1;
+    const Layout with = layout(d, d.KS, true, d.smp_bufs);
+    const Layout without = layout(d, d.KS, false, d.smp_bufs);
     const bool prog = with.total <= kLdsLimit / 2 || (with.total <= kLdsLimit && without.total > kLdsLimit / 2);
     const Layout& L = prog ? with : without;
     if (L.total > kLdsLimit) return hipErrorNotSupported;
@@ -413,7 +429,7 @@ hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
         KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog);
         if (!fn) return hipErrorNotSupported;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
         if (e != hipSuccess) return e;
         int blocks = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn), d.threads,
@@ -427,7 +443,7 @@ hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
 
 hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
     const bool prog = d.prog_lds != 0;
-    const Layout L = layout(d, d.KS, prog);
+    const Layout L = layout(d, d.KS, prog, d.smp_bufs);
     Fp32Args a{};
     a.samples = samples;
     a.T = n_time;
@@ -441,6 +457,7 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.off_w = L.off_w; a.off_gant = L.off_gant; a.off_desc = L.off_desc;
     a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw;
     a.nibble_order = d.nibble_order;
+    a.dbuf = d.smp_bufs == 2 ? 1 : 0;
     a.grid_wg = d.grid_wg;
     a.wg_per_xcd = (d.grid_wg + 7) / 8;
     KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog);

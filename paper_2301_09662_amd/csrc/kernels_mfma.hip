@@ -27,6 +27,7 @@
 #include "epic_device.hpp"
 #include "epic_gather.hpp"
 #include "epic_internal.hpp"
+#include "epic_sched.hpp"
 
 namespace epic {
 
@@ -36,20 +37,32 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-struct MfmaArgs {
+// One sub-array as the segment function sees it.
+struct SegCtx {
     const uint8_t* samples;   // [T][C][A][P]
-    int64_t T;
-    int C, A, S;
     const ChanInfo* chans;
     const CellDesc* cells_desc;
     const uint2* grp_ant;
     const float4* grp_w;
     const _Float16* dft;      // [2N][K2] real-form DFT matrix, row-major
     float* slots;             // [S][C][NPP][N][N]
+    int C, A;
     int WP;                   // pitch encoded in the gather program's cell offsets
     int M1max;                // rows of the row-pass operand (multiple of 16)
+    int nibble_order, prog_lds;
+};
+
+// LDS carve-up shared by every segment a workgroup runs.
+struct LdsMap {
     uint32_t off_w, off_gant, off_desc, off_smp, off_A1, off_B2;
-    int nibble_order;
+    int smp_stride;           // float2 elements between the two sample buffers
+};
+
+struct MfmaArgs {
+    SegCtx sc;
+    LdsMap lm;
+    int64_t T;
+    int V;                    // virtual channels C * KS
     int grid_wg, wg_per_xcd;
 };
 
@@ -63,7 +76,6 @@ struct MShape {
     static constexpr int NK = N / KS;              // columns per workgroup
     static constexpr int IT = NK / 16;             // 16-column tiles per workgroup
     static constexpr int WAVES = N / 16;           // one wave per 16 image rows
-    static constexpr int THREADS = 64 * WAVES;
     static constexpr int NT1 = 2 / KS;             // row-pass output tiles per wave
     static constexpr int A1P = K2 + 8;             // LDS pitches (halfs)
     static constexpr int B2P = K2 + 8;
@@ -76,36 +88,60 @@ __device__ __forceinline__ floatx4 mfma16(half8 a, half8 b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-template <int N_, int KK_, int P, bool REAL, bool PROG_LDS>
-__global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
+// Gather gridding of every non-empty window cell (FP32 sums), stored as the
+// FP16 row-pass operand: row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)].
+// The program pointers are all in LDS or all in global memory.
+template <int P, bool REAL, int KPAD, int A1P, int TH, typename DescP, typename AntP, typename WP_>
+__device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int n_cell,
+                                             const float2* __restrict__ smp, int WP, int R4, _Float16* s_A1) {
+    constexpr int GF4 = group_f4<P, REAL>();
+    for (int k = threadIdx.x; k < n_cell; k += TH) {
+        const uint2 d = desc[k];
+        const int off = (int)(d.x & 0xFFFFu);
+        const int ng = (int)(d.x >> 16);
+        float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
+        for (int j = 0; j < ng; ++j) {
+            const int gg = (int)d.y + j;
+            gather_group<P, REAL>(gx, gy, wts + (int64_t)gg * GF4, gant[gg], smp);
+        }
+        const int r = off / WP, w = off - r * WP;
+        _Float16* dst = s_A1 + r * A1P + w;
+        dst[0] = (_Float16)gx.x;
+        dst[KPAD] = (_Float16)gx.y;
+        if constexpr (P == 2) {
+            dst[R4 * A1P] = (_Float16)gy.x;
+            dst[R4 * A1P + KPAD] = (_Float16)gy.y;
+        }
+    }
+}
+
+// Process spectra [k0, k1) (index v*T + t, v = virtual channel) of one
+// sub-array with TH threads; waves beyond N/16 only help with the decoding,
+// gathering and clearing.  The spectra's cost offsets are base + k*w in units
+// where one workgroup's share is Lc (slot choice in slot_of).
+template <int N_, int KK_, int P, bool REAL, int TH>
+__device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, unsigned char* smem, int64_t T, int g,
+                                         int64_t k0, int64_t k1, int64_t base, int64_t w_cost, int64_t Lc) {
     using Sh = MShape<N_, KK_>;
     constexpr int N = Sh::N, KK = Sh::KK, KPAD = Sh::KPAD, K2 = Sh::K2, KS = Sh::KS, NK = Sh::NK;
-    constexpr int IT = Sh::IT, THREADS = Sh::THREADS, NT1 = Sh::NT1, A1P = Sh::A1P, B2P = Sh::B2P;
+    constexpr int IT = Sh::IT, NT1 = Sh::NT1, A1P = Sh::A1P, B2P = Sh::B2P, WAVES = Sh::WAVES;
     constexpr int NPP = (P == 2) ? 4 : 1;
     constexpr int GF4 = group_f4<P, REAL>();
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l16 = lane & 15, l4 = lane >> 4;
+    const bool mwave = (TH == 64 * WAVES) || wave < WAVES;   // waves owning image rows
+    const int mw = mwave ? wave : 0;
+    const bool prog = sc.prog_lds != 0;
 
-    const int b = blockIdx.x;
-    const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
-    if (g >= a.grid_wg) return;
-    const int64_t T = a.T;
-    const int64_t total = (int64_t)a.C * KS * T;
-    const int64_t L = (total + a.grid_wg - 1) / a.grid_wg;
-    const int64_t f0 = (int64_t)g * L;
-    const int64_t f1 = (f0 + L < total) ? f0 + L : total;
-    if (f0 >= f1) return;
-
-    extern __shared__ __align__(16) unsigned char smem[];
-    float4* s_w = reinterpret_cast<float4*>(smem + a.off_w);
-    uint2* s_gant = reinterpret_cast<uint2*>(smem + a.off_gant);
-    uint2* s_desc = reinterpret_cast<uint2*>(smem + a.off_desc);
-    float2* s_smp0 = reinterpret_cast<float2*>(smem + a.off_smp);   // two sample buffers
-    float2* s_smp1 = s_smp0 + a.A * P;
-    _Float16* s_A1 = reinterpret_cast<_Float16*>(smem + a.off_A1);
-    _Float16* s_B2 = reinterpret_cast<_Float16*>(smem + a.off_B2);
+    float4* s_w = reinterpret_cast<float4*>(smem + lm.off_w);
+    uint2* s_gant = reinterpret_cast<uint2*>(smem + lm.off_gant);
+    uint2* s_desc = reinterpret_cast<uint2*>(smem + lm.off_desc);
+    float2* s_smp0 = reinterpret_cast<float2*>(smem + lm.off_smp);   // two sample buffers
+    float2* s_smp1 = s_smp0 + lm.smp_stride;
+    _Float16* s_A1 = reinterpret_cast<_Float16*>(smem + lm.off_A1);
+    _Float16* s_B2 = reinterpret_cast<_Float16*>(smem + lm.off_B2);
 
     // column-pass operand: rows 16w.. (real part) and N + 16w.. (imaginary part)
     half8 a2[2][KK];
@@ -113,92 +149,90 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int ks = 0; ks < KK; ++ks)
-            a2[h][ks] = *reinterpret_cast<const half8*>(a.dft + (size_t)(h * N + 16 * wave + l16) * K2 + 32 * ks +
+            a2[h][ks] = *reinterpret_cast<const half8*>(sc.dft + (size_t)(h * N + 16 * mw + l16) * K2 + 32 * ks +
                                                         8 * l4);
 
-    const int AP = a.A * P;
-    const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.samples) & 3) == 0);
+    const int AP = sc.A * P;
+    const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(sc.samples) & 3) == 0);
     const int nwords = AP >> 2;
-
     constexpr int kPre = 1;   // sample words per thread loaded one spectrum ahead (more are loaded directly)
     uint32_t pre[kPre];
     auto prefetch = [&](int vv, int64_t tt) {
         const uint32_t* row4 =
-            reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + vv / KS) * AP);
+            reinterpret_cast<const uint32_t*>(sc.samples + ((int64_t)tt * sc.C + vv / KS) * AP);
 #pragma unroll
         for (int k = 0; k < kPre; ++k) {
-            const int w = tid + k * THREADS;
+            const int w = tid + k * TH;
             pre[k] = (w < nwords) ? row4[w] : 0u;
         }
     };
-
     // decode one (t, c) row of A*P bytes into dst: the prefetched words first,
     // any further words straight from memory
     auto decode = [&](float2* dst, int cc, int64_t tt) {
         if (words) {
 #pragma unroll
             for (int k = 0; k < kPre; ++k) {
-                const int w = tid + k * THREADS;
+                const int w = tid + k * TH;
                 if (w < nwords) {
                     const uint32_t x = pre[k];
-                    dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                    dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                    dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                    dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                    dst[4 * w + 0] = unpack44(x & 0xFFu, sc.nibble_order);
+                    dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, sc.nibble_order);
+                    dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, sc.nibble_order);
+                    dst[4 * w + 3] = unpack44(x >> 24, sc.nibble_order);
                 }
             }
-            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
-            for (int w = tid + kPre * THREADS; w < nwords; w += THREADS) {
+            const uint32_t* row4 = reinterpret_cast<const uint32_t*>(sc.samples + ((int64_t)tt * sc.C + cc) * AP);
+            for (int w = tid + kPre * TH; w < nwords; w += TH) {
                 const uint32_t x = row4[w];
-                dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                dst[4 * w + 0] = unpack44(x & 0xFFu, sc.nibble_order);
+                dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, sc.nibble_order);
+                dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, sc.nibble_order);
+                dst[4 * w + 3] = unpack44(x >> 24, sc.nibble_order);
             }
         } else {
-            const uint8_t* row = a.samples + ((int64_t)tt * a.C + cc) * AP;
-            for (int k = tid; k < AP; k += THREADS) dst[k] = unpack44(row[k], a.nibble_order);
+            const uint8_t* row = sc.samples + ((int64_t)tt * sc.C + cc) * AP;
+            for (int k = tid; k < AP; k += TH) dst[k] = unpack44(row[k], sc.nibble_order);
         }
     };
 
-    int v = (int)(f0 / T);
-    int64_t t = f0 - (int64_t)v * T;
+    int v = (int)(k0 / T);
+    int64_t t = k0 - (int64_t)v * T;
     if (words) prefetch(v, t);
-    for (int64_t f = f0; f < f1;) {
+    for (int64_t f = k0; f < k1;) {
         // one channel segment: spectra t .. t+n-1 of virtual channel v
-        const int64_t n = (f1 - f < T - t) ? f1 - f : T - t;
+        const int64_t n = (k1 - f < T - t) ? k1 - f : T - t;
         const int c = v / KS;
         const int kpart = v - c * KS;
-        const int slot = g - (int)(((int64_t)v * T) / L);
-        const ChanInfo ci = a.chans[c];
+        const int slot = slot_of(g, v, t, T, base, w_cost, Lc);
+        const ChanInfo ci = sc.chans[c];
         const int n_cell = ci.n_cell;
         const int R4 = (ci.R + 3) & ~3;
         const int M1 = P * R4;
-        const CellDesc* g_desc = a.cells_desc + ci.cell_off;
-        const uint2* g_gant = a.grp_ant + ci.grp_off;
-        const float4* g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
+        const CellDesc* g_desc = sc.cells_desc + ci.cell_off;
+        const uint2* g_gant = sc.grp_ant + ci.grp_off;
+        const float4* g_w = sc.grp_w + (int64_t)ci.grp_off * GF4;
         half8 b1[NT1][KK];   // row-pass operand for this wave's output tiles
 #pragma unroll
         for (int u = 0; u < NT1; ++u) {
-            const int nloc = 16 * (wave * NT1 + u) + l16;          // own-column index in [0, 2 NK)
+            const int nloc = 16 * (mw * NT1 + u) + l16;          // own-column index in [0, 2 NK)
             const int row = (nloc < NK) ? kpart * NK + nloc : N + kpart * NK + (nloc - NK);
 #pragma unroll
             for (int ks = 0; ks < KK; ++ks)
-                b1[u][ks] = *reinterpret_cast<const half8*>(a.dft + (size_t)row * K2 + 32 * ks + 8 * l4);
+                b1[u][ks] = *reinterpret_cast<const half8*>(sc.dft + (size_t)row * K2 + 32 * ks + 8 * l4);
         }
         __syncthreads();   // the previous segment is done with every LDS buffer
-        if constexpr (PROG_LDS) {
-            for (int k = tid; k < ci.n_grp * GF4; k += THREADS) s_w[k] = g_w[k];
-            for (int k = tid; k < ci.n_grp; k += THREADS) s_gant[k] = g_gant[k];
-            for (int k = tid; k < n_cell; k += THREADS) s_desc[k] = g_desc[k];
+        if (prog) {
+            for (int k = tid; k < ci.n_grp * GF4; k += TH) s_w[k] = g_w[k];
+            for (int k = tid; k < ci.n_grp; k += TH) s_gant[k] = g_gant[k];
+            for (int k = tid; k < n_cell; k += TH) s_desc[k] = g_desc[k];
         }
         // zero both operand buffers: cells outside the window, rows beyond R
         // and the padding up to whole MFMA steps are never written again
         {
             uint4* z1 = reinterpret_cast<uint4*>(s_A1);
-            for (int k = tid; k < a.M1max * A1P / 8; k += THREADS) z1[k] = make_uint4(0, 0, 0, 0);
+            for (int k = tid; k < sc.M1max * A1P / 8; k += TH) z1[k] = make_uint4(0, 0, 0, 0);
             uint4* z2 = reinterpret_cast<uint4*>(s_B2);
-            for (int k = tid; k < P * NK * B2P / 8; k += THREADS) z2[k] = make_uint4(0, 0, 0, 0);
+            for (int k = tid; k < P * NK * B2P / 8; k += TH) z2[k] = make_uint4(0, 0, 0, 0);
         }
         float acc[IT][4][NPP];
 #pragma unroll
@@ -211,7 +245,7 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
         // decode the segment's first spectrum (the rest are decoded one step
         // ahead, into the other sample buffer, while the current one is gridded)
         decode(s_smp0, c, t);
-        if (words && f + 1 < f1) {
+        if (words && f + 1 < k1) {
             if (t + 1 < T) prefetch(v, t + 1);
             else prefetch(v + 1, 0);
         }
@@ -224,30 +258,14 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
 
             // 2. gather gridding (FP32), stored as the FP16 row-pass operand:
             //    row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)]
-            for (int k = tid; k < n_cell; k += THREADS) {
-                const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
-                const int off = (int)(d.x & 0xFFFFu);
-                const int ng = (int)(d.x >> 16);
-                float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
-                for (int j = 0; j < ng; ++j) {
-                    const int gg = (int)d.y + j;
-                    const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
-                    const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
-                    gather_group<P, REAL>(gx, gy, w, ia, s_smp);
-                }
-                const int r = off / a.WP, w = off - r * a.WP;
-                _Float16* dst = s_A1 + r * A1P + w;
-                dst[0] = (_Float16)gx.x;
-                dst[KPAD] = (_Float16)gx.y;
-                if constexpr (P == 2) {
-                    dst[R4 * A1P] = (_Float16)gy.x;
-                    dst[R4 * A1P + KPAD] = (_Float16)gy.y;
-                }
-            }
+            if (prog)
+                gather_cells<P, REAL, KPAD, A1P, TH>(s_desc, s_gant, s_w, n_cell, s_smp, sc.WP, R4, s_A1);
+            else
+                gather_cells<P, REAL, KPAD, A1P, TH>(g_desc, g_gant, g_w, n_cell, s_smp, sc.WP, R4, s_A1);
             // 1'. decode the next spectrum of this segment into the other buffer
             if (i + 1 < n) {
                 decode(s_nxt, c, tt + 1);
-                if (words && f + i + 2 < f1) {
+                if (words && f + i + 2 < k1) {
                     if (tt + 2 < T) prefetch(v, tt + 2);
                     else prefetch(v + 1, 0);
                 }
@@ -257,26 +275,29 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
             // 3a. row pass: [M1 x K2] x [K2 x 2 NK] on the matrix cores; each wave
             //     takes NT1 output tiles and writes them, rounded to FP16, as the
             //     column-pass operand B2[p][i][Re Y(0..) | Im Y(0..)]
-            for (int mt = 0; mt < (M1 + 15) / 16; ++mt) {
-                half8 af[KK];
+            if (mwave) {
+                for (int mt = 0; mt < (M1 + 15) / 16; ++mt) {
+                    half8 af[KK];
 #pragma unroll
-                for (int ks = 0; ks < KK; ++ks)
-                    af[ks] = *reinterpret_cast<const half8*>(s_A1 + (16 * mt + l16) * A1P + 32 * ks + 8 * l4);
-                const int m0 = 16 * mt + 4 * l4;
+                    for (int ks = 0; ks < KK; ++ks)
+                        af[ks] = *reinterpret_cast<const half8*>(s_A1 + (16 * mt + l16) * A1P + 32 * ks + 8 * l4);
+                    const int m0 = 16 * mt + 4 * l4;
 #pragma unroll
-                for (int u = 0; u < NT1; ++u) {
-                    floatx4 d = {0.f, 0.f, 0.f, 0.f};
+                    for (int u = 0; u < NT1; ++u) {
+                        floatx4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int ks = 0; ks < KK; ++ks) d = mfma16(af[ks], b1[u][ks], d);
-                    if (m0 < M1) {
-                        const int p = (P == 2 && m0 >= R4) ? 1 : 0;
-                        const int r0 = m0 - p * R4;
-                        const int nloc = 16 * (wave * NT1 + u) + l16;
-                        const int part = nloc >= NK ? 1 : 0;
-                        const int iloc = nloc - part * NK;
-                        half4 hv;
-                        hv[0] = (_Float16)d[0]; hv[1] = (_Float16)d[1]; hv[2] = (_Float16)d[2]; hv[3] = (_Float16)d[3];
-                        *reinterpret_cast<half4*>(s_B2 + (p * NK + iloc) * B2P + part * KPAD + r0) = hv;
+                        for (int ks = 0; ks < KK; ++ks) d = mfma16(af[ks], b1[u][ks], d);
+                        if (m0 < M1) {
+                            const int p = (P == 2 && m0 >= R4) ? 1 : 0;
+                            const int r0 = m0 - p * R4;
+                            const int nloc = 16 * (mw * NT1 + u) + l16;
+                            const int part = nloc >= NK ? 1 : 0;
+                            const int iloc = nloc - part * NK;
+                            half4 hv;
+                            hv[0] = (_Float16)d[0]; hv[1] = (_Float16)d[1];
+                            hv[2] = (_Float16)d[2]; hv[3] = (_Float16)d[3];
+                            *reinterpret_cast<half4*>(s_B2 + (p * NK + iloc) * B2P + part * KPAD + r0) = hv;
+                        }
                     }
                 }
             }
@@ -284,47 +305,51 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
 
             // 3b + 4. column pass: E~ rows 16w.. for every own column tile, both
             //         pols, then the products of Eq. 5 accumulated in registers
+            if (mwave) {
 #pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                floatx4 er[P], ei[P];
+                for (int it = 0; it < IT; ++it) {
+                    floatx4 er[P], ei[P];
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    er[p] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    ei[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    for (int p = 0; p < P; ++p) {
+                        er[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        ei[p] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int ks = 0; ks < KK; ++ks) {
-                        const half8 bf = *reinterpret_cast<const half8*>(s_B2 + (p * NK + 16 * it + l16) * B2P +
-                                                                         32 * ks + 8 * l4);
-                        er[p] = mfma16(a2[0][ks], bf, er[p]);
-                        ei[p] = mfma16(a2[1][ks], bf, ei[p]);
+                        for (int ks = 0; ks < KK; ++ks) {
+                            const half8 bf = *reinterpret_cast<const half8*>(
+                                s_B2 + (p * NK + 16 * it + l16) * B2P + 32 * ks + 8 * l4);
+                            er[p] = mfma16(a2[0][ks], bf, er[p]);
+                            ei[p] = mfma16(a2[1][ks], bf, ei[p]);
+                        }
                     }
-                }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float xr = er[0][e], xi = ei[0][e];
-                    acc[it][e][0] = fmaf(xr, xr, fmaf(xi, xi, acc[it][e][0]));
-                    if constexpr (P == 2) {
-                        const float yr = er[1][e], yi = ei[1][e];
-                        acc[it][e][1] = fmaf(yr, yr, fmaf(yi, yi, acc[it][e][1]));
-                        acc[it][e][2] = fmaf(xr, yr, fmaf(xi, yi, acc[it][e][2]));
-                        acc[it][e][3] = fmaf(xi, yr, fmaf(-xr, yi, acc[it][e][3]));
+                    for (int e = 0; e < 4; ++e) {
+                        const float xr = er[0][e], xi = ei[0][e];
+                        acc[it][e][0] = fmaf(xr, xr, fmaf(xi, xi, acc[it][e][0]));
+                        if constexpr (P == 2) {
+                            const float yr = er[1][e], yi = ei[1][e];
+                            acc[it][e][1] = fmaf(yr, yr, fmaf(yi, yi, acc[it][e][1]));
+                            acc[it][e][2] = fmaf(xr, yr, fmaf(xi, yi, acc[it][e][2]));
+                            acc[it][e][3] = fmaf(xi, yr, fmaf(-xr, yi, acc[it][e][3]));
+                        }
                     }
                 }
             }
         }
 
         // add the segment's sums into its slot; bin -> pixel (+N/2 mod N)
-        float* base = a.slots + ((int64_t)slot * a.C + c) * NPP * N * N;
+        if (mwave) {
+            float* base_p = sc.slots + ((int64_t)slot * sc.C + c) * NPP * N * N;
 #pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            int ii = kpart * NK + 16 * it + l16 + N / 2;
-            if (ii >= N) ii -= N;
+            for (int it = 0; it < IT; ++it) {
+                int ii = kpart * NK + 16 * it + l16 + N / 2;
+                if (ii >= N) ii -= N;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int j = 16 * wave + 4 * l4 + e + N / 2;
-                if (j >= N) j -= N;
+                for (int e = 0; e < 4; ++e) {
+                    int j = 16 * mw + 4 * l4 + e + N / 2;
+                    if (j >= N) j -= N;
 #pragma unroll
-                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + ii] += acc[it][e][k];
+                    for (int k = 0; k < NPP; ++k) base_p[((int64_t)k * N + j) * N + ii] += acc[it][e][k];
+                }
             }
         }
         f += n;
@@ -333,56 +358,132 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
     }
 }
 
+// One sub-array: persistent, equal contiguous runs of the (channel, spectrum)
+// sequence, XCD-aware (consecutive runs share an XCD's L2).
+template <int N_, int KK_, int P, bool REAL>
+__global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
+    const int b = blockIdx.x;
+    const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
+    if (g >= a.grid_wg) return;
+    const int64_t total = (int64_t)a.V * a.T;
+    const int64_t L = (total + a.grid_wg - 1) / a.grid_wg;
+    int64_t k0, k1;
+    owned_range(g, L, 0, 1, total, &k0, &k1);
+    if (k0 >= k1) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    mfma_run<N_, KK_, P, REAL, mfma_threads<N_>()>(a.sc, a.lm, smem, a.T, g, k0, k1, 0, 1, L);
+}
+
+// ---- several sub-arrays in one persistent launch ---------------------------
+// The spectra of all sub-arrays form one sequence in which a spectrum of
+// sub-array s costs w_s units (a cost model, or times measured by the plan's
+// autotuner); workgroup g takes every spectrum whose cost offset falls in
+// [g L, (g+1) L), L = ceil(total / G), so uneven sub-arrays still give every
+// workgroup the same work.  Each sub-array runs its own compiled shape.
+constexpr int kBatchThreads = 384;   // 6 waves: one per 16 image rows up to N = 96
+
+struct BatchArgs {
+    const uint8_t* samples[kMaxSub];
+    const BatchSub* subs;     // device table [n_sub]
+    LdsMap lm;
+    int n_sub;
+    int64_t T;
+    int grid_wg, wg_per_xcd;
+};
+
+// (N, KK) shapes a batched launch can run
+#define EPIC_BATCH_SHAPES(F)                                                              \
+    F(32, 1) F(32, 2) F(48, 1) F(48, 2) F(48, 3) F(64, 1) F(64, 2) F(64, 3) F(64, 4)      \
+    F(96, 1) F(96, 2) F(96, 3) F(96, 4)
+
+template <int P, bool REAL>
+__global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchArgs a) {
+    const int b = blockIdx.x;
+    const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
+    if (g >= a.grid_wg) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t total = 0;
+    for (int s = 0; s < a.n_sub; ++s) total += (int64_t)a.subs[s].V * a.T * a.subs[s].weight;
+    const int64_t Lc = (total + a.grid_wg - 1) / a.grid_wg;
+    int64_t base = 0;
+    for (int s = 0; s < a.n_sub; ++s) {
+        const BatchSub& bs = a.subs[s];
+        const int64_t items = (int64_t)bs.V * a.T;
+        const int64_t w = bs.weight;
+        int64_t k0, k1;
+        owned_range(g, Lc, base, w, items, &k0, &k1);
+        if (k0 < k1) {
+            SegCtx sc;
+            sc.samples = a.samples[s];
+            sc.chans = bs.chans;
+            sc.cells_desc = bs.cells_desc;
+            sc.grp_ant = reinterpret_cast<const uint2*>(bs.grp_ant);
+            sc.grp_w = reinterpret_cast<const float4*>(bs.grp_w);
+            sc.dft = reinterpret_cast<const _Float16*>(bs.dft);
+            sc.slots = bs.slots;
+            sc.C = bs.C; sc.A = bs.A; sc.WP = bs.WP; sc.M1max = bs.M1max;
+            sc.nibble_order = bs.nibble_order; sc.prog_lds = bs.prog_lds;
+            switch (bs.N * 8 + bs.KK) {
+#define EPIC_RUN(NN, KKK)                                                                           \
+    case NN * 8 + KKK:                                                                              \
+        mfma_run<NN, KKK, P, REAL, kBatchThreads>(sc, a.lm, smem, a.T, g, k0, k1, base, w, Lc);     \
+        break;
+                EPIC_BATCH_SHAPES(EPIC_RUN)
+#undef EPIC_RUN
+            }
+        }
+        base += items * w;
+    }
+}
+
 // ---- launch shapes -----------------------------------------------------------
 struct Layout {
-    uint32_t off_w, off_gant, off_desc, off_smp, off_A1, off_B2;
+    LdsMap lm;
     size_t total;
     int M1max;
 };
 
 int ks_of(int N) { return N > 64 ? 2 : 1; }
 
+size_t take_aligned(size_t& b, size_t n) {
+    b = (b + 15) & ~(size_t)15;
+    const size_t o = b;
+    b += n;
+    return o;
+}
+
+int m1max_of(const SubDev& d) { return (d.P * ((d.Rmax + 3) & ~3) + 15) / 16 * 16; }
+
 Layout layout(const SubDev& d, bool prog_lds) {
     Layout L{};
     size_t b = 0;
-    auto take = [&](size_t n) {
-        b = (b + 15) & ~(size_t)15;
-        size_t o = b;
-        b += n;
-        return (uint32_t)o;
-    };
     const int gf4 = d.real_taps ? (d.P == 2 ? 2 : 1) : (d.P == 2 ? 4 : 2);
     const int K2 = 32 * d.KK;
     const int NK = d.N / ks_of(d.N);
-    const int R4max = (d.Rmax + 3) & ~3;
-    L.M1max = (d.P * R4max + 15) / 16 * 16;
-    L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
-    L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
-    L.off_desc = prog_lds ? take((size_t)d.CellMax * 8) : 0;
-    L.off_smp = take((size_t)2 * d.A * d.P * sizeof(float2));
-    L.off_A1 = take((size_t)L.M1max * (K2 + 8) * 2);
-    L.off_B2 = take((size_t)d.P * NK * (K2 + 8) * 2);
+    L.M1max = m1max_of(d);
+    L.lm.off_w = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.Gmax * gf4 * 16) : 0;
+    L.lm.off_gant = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.Gmax * 8) : 0;
+    L.lm.off_desc = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.CellMax * 8) : 0;
+    L.lm.off_smp = (uint32_t)take_aligned(b, (size_t)2 * d.A * d.P * sizeof(float2));
+    L.lm.smp_stride = d.A * d.P;
+    L.lm.off_A1 = (uint32_t)take_aligned(b, (size_t)L.M1max * (K2 + 8) * 2);
+    L.lm.off_B2 = (uint32_t)take_aligned(b, (size_t)d.P * NK * (K2 + 8) * 2);
     L.total = (b + 15) & ~(size_t)15;
     return L;
 }
 
 using KernelFn = void (*)(MfmaArgs);
 
-template <int N, int KK, int P>
-KernelFn pick3(bool real, bool prog) {
-    if (real) return prog ? mfma_kernel<N, KK, P, true, true> : mfma_kernel<N, KK, P, true, false>;
-    return prog ? mfma_kernel<N, KK, P, false, true> : mfma_kernel<N, KK, P, false, false>;
-}
-
 template <int N, int KK>
-KernelFn pick2(int P, bool real, bool prog) {
-    return P == 2 ? pick3<N, KK, 2>(real, prog) : pick3<N, KK, 1>(real, prog);
+KernelFn pick2(int P, bool real) {
+    if (P == 2) return real ? mfma_kernel<N, KK, 2, true> : mfma_kernel<N, KK, 2, false>;
+    return real ? mfma_kernel<N, KK, 1, true> : mfma_kernel<N, KK, 1, false>;
 }
 
-// Grid sizes 32..128 (multiples of 16) with window depth KK*16 <= min(N, 64).
-KernelFn select_kernel(int N, int KK, int P, bool real, bool prog) {
+// Grid sizes 32..128 (multiples of 16, not 80 / 112) with window depth KK*16 <= min(N, 64).
+KernelFn select_kernel(int N, int KK, int P, bool real) {
     switch (N * 8 + KK) {
-#define EPIC_K(NN, KKK) case NN * 8 + KKK: return pick2<NN, KKK>(P, real, prog);
+#define EPIC_K(NN, KKK) case NN * 8 + KKK: return pick2<NN, KKK>(P, real);
         EPIC_K(32, 1) EPIC_K(32, 2)
         EPIC_K(48, 1) EPIC_K(48, 2) EPIC_K(48, 3)
         EPIC_K(64, 1) EPIC_K(64, 2) EPIC_K(64, 3) EPIC_K(64, 4)
@@ -393,7 +494,27 @@ KernelFn select_kernel(int N, int KK, int P, bool real, bool prog) {
     return nullptr;
 }
 
+using BatchFn = void (*)(BatchArgs);
+
+BatchFn select_batch(int P, bool real) {
+    if (P == 2) return real ? batch_kernel<2, true> : batch_kernel<2, false>;
+    return real ? batch_kernel<1, true> : batch_kernel<1, false>;
+}
+
+bool batch_shape_ok(int N, int KK) {
+    switch (N * 8 + KK) {
+#define EPIC_OK_CASE(NN, KKK) case NN * 8 + KKK: return true;
+        EPIC_BATCH_SHAPES(EPIC_OK_CASE)
+#undef EPIC_OK_CASE
+    }
+    return false;
+}
+
 constexpr size_t kLdsLimit = 160 * 1024;
+
+bool prefer_prog(size_t with, size_t without) {
+    return with <= kLdsLimit / 2 || (with <= kLdsLimit && without > kLdsLimit / 2);
+}
 
 // FP64 real-form DFT matrix M[2N][K2]: row n (i = n mod N), column k
 // (w = k mod KPAD): [[cos, -sin], [sin, cos]] of 2 pi (w i mod N) / N, i.e.
@@ -423,17 +544,17 @@ hipError_t mfma_configure(SubDev& d, int device, int num_cu) {
     d.threads = 64 * (d.N / 16);
     const Layout with = layout(d, true);
     const Layout without = layout(d, false);
-    const bool prog = with.total <= kLdsLimit / 2 || (with.total <= kLdsLimit && without.total > kLdsLimit / 2);
+    const bool prog = prefer_prog(with.total, without.total);
     const Layout& L = prog ? with : without;
     if (L.total > kLdsLimit) return hipErrorNotSupported;
     d.lds_bytes = L.total;
     d.prog_lds = prog ? 1 : 0;
     int occ = 2;
     if (device >= 0) {
-        KernelFn fn = select_kernel(d.N, d.KK, d.P, d.real_taps != 0, prog);
+        KernelFn fn = select_kernel(d.N, d.KK, d.P, d.real_taps != 0);
         if (!fn) return hipErrorNotSupported;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
         if (e != hipSuccess) return e;
         int blocks = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn), d.threads,
@@ -453,28 +574,129 @@ hipError_t launch_dft_matrix(const SubDev& d, hipStream_t st) {
 }
 
 hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
-    const bool prog = d.prog_lds != 0;
-    const Layout L = layout(d, prog);
+    const Layout L = layout(d, d.prog_lds != 0);
     MfmaArgs a{};
-    a.samples = samples;
+    a.sc.samples = samples;
+    a.sc.chans = d.chans;
+    a.sc.cells_desc = d.cells_desc;
+    a.sc.grp_ant = reinterpret_cast<const uint2*>(d.grp_ant);
+    a.sc.grp_w = reinterpret_cast<const float4*>(d.grp_w);
+    a.sc.dft = reinterpret_cast<const _Float16*>(d.dft16);
+    a.sc.slots = d.slots;
+    a.sc.C = d.C; a.sc.A = d.A; a.sc.WP = d.WP; a.sc.M1max = L.M1max;
+    a.sc.nibble_order = d.nibble_order; a.sc.prog_lds = d.prog_lds;
+    a.lm = L.lm;
     a.T = n_time;
-    a.C = d.C; a.A = d.A; a.S = d.S;
-    a.chans = d.chans;
-    a.cells_desc = d.cells_desc;
-    a.grp_ant = reinterpret_cast<const uint2*>(d.grp_ant);
-    a.grp_w = reinterpret_cast<const float4*>(d.grp_w);
-    a.dft = reinterpret_cast<const _Float16*>(d.dft16);
-    a.slots = d.slots;
-    a.WP = d.WP;
-    a.M1max = L.M1max;
-    a.off_w = L.off_w; a.off_gant = L.off_gant; a.off_desc = L.off_desc;
-    a.off_smp = L.off_smp; a.off_A1 = L.off_A1; a.off_B2 = L.off_B2;
-    a.nibble_order = d.nibble_order;
+    a.V = d.C * d.KS;
     a.grid_wg = d.grid_wg;
     a.wg_per_xcd = (d.grid_wg + 7) / 8;
-    KernelFn fn = select_kernel(d.N, d.KK, d.P, d.real_taps != 0, prog);
+    KernelFn fn = select_kernel(d.N, d.KK, d.P, d.real_taps != 0);
     if (!fn) return hipErrorNotSupported;
     hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(d.threads), L.total, st, a);
+    return hipGetLastError();
+}
+
+// Shared launch shape of a batched plan: the LDS layout holds the largest of
+// every buffer over the sub-arrays; the gather programs live in LDS only if
+// all of them fit.  Every sub-array must be an FP16 shape of the batch
+// catalogue with the same pol count and tap kind.  Fills bd (not the device
+// table, which the caller builds once slots and weights are known).
+hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, int num_cu) {
+    const int P = subs[0].P, real = subs[0].real_taps;
+    size_t gw = 0, ga = 0, gd = 0, smp = 0, a1 = 0, b2 = 0;
+    for (int s = 0; s < n_sub; ++s) {
+        SubDev& d = subs[s];
+        if (d.P != P || d.real_taps != real) return hipErrorNotSupported;
+        d.KK = (std::max(d.Rmax, d.Wmax) + 15) / 16;
+        if (!batch_shape_ok(d.N, d.KK)) return hipErrorNotSupported;
+        d.KS = ks_of(d.N);
+        const int gf4 = real ? (P == 2 ? 2 : 1) : (P == 2 ? 4 : 2);
+        gw = std::max(gw, (size_t)d.Gmax * gf4 * 16);
+        ga = std::max(ga, (size_t)d.Gmax * 8);
+        gd = std::max(gd, (size_t)d.CellMax * 8);
+        smp = std::max(smp, (size_t)d.A * d.P);
+        const int K2 = 32 * d.KK;
+        a1 = std::max(a1, (size_t)m1max_of(d) * (K2 + 8) * 2);
+        b2 = std::max(b2, (size_t)d.P * (d.N / d.KS) * (K2 + 8) * 2);
+    }
+    auto lay = [&](bool prog, LdsMap& lm) {
+        size_t b = 0;
+        lm.off_w = prog ? (uint32_t)take_aligned(b, gw) : 0;
+        lm.off_gant = prog ? (uint32_t)take_aligned(b, ga) : 0;
+        lm.off_desc = prog ? (uint32_t)take_aligned(b, gd) : 0;
+        lm.off_smp = (uint32_t)take_aligned(b, 2 * smp * sizeof(float2));
+        lm.smp_stride = (int)smp;
+        lm.off_A1 = (uint32_t)take_aligned(b, a1);
+        lm.off_B2 = (uint32_t)take_aligned(b, b2);
+        return (b + 15) & ~(size_t)15;
+    };
+    LdsMap lw{}, ln{};
+    const size_t tw = lay(true, lw), tn = lay(false, ln);
+    const bool prog = prefer_prog(tw, tn);
+    const size_t total = prog ? tw : tn;
+    if (total > kLdsLimit) return hipErrorNotSupported;
+    const LdsMap& lm = prog ? lw : ln;
+    bd.off[0] = lm.off_w; bd.off[1] = lm.off_gant; bd.off[2] = lm.off_desc;
+    bd.off[3] = lm.off_smp; bd.off[4] = lm.off_A1; bd.off[5] = lm.off_B2;
+    bd.smp_stride = lm.smp_stride;
+    bd.lds_bytes = total;
+    bd.prog_lds = prog ? 1 : 0;
+    bd.P = P;
+    bd.real = real;
+    bd.threads = kBatchThreads;
+    bd.kkmax = 0;
+    int occ = 1;
+    if (device >= 0) {
+        BatchFn fn = select_batch(P, real != 0);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+        if (e != hipSuccess) return e;
+        int blocks = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn), kBatchThreads,
+                                                         total);
+        if (e != hipSuccess) return e;
+        occ = blocks > 0 ? blocks : 1;
+    }
+    bd.grid_wg = ((num_cu * occ + 7) / 8) * 8;
+    for (int s = 0; s < n_sub; ++s) {
+        subs[s].threads = kBatchThreads;
+        subs[s].lds_bytes = total;
+        subs[s].prog_lds = bd.prog_lds;
+        subs[s].grid_wg = bd.grid_wg;
+    }
+    return hipSuccess;
+}
+
+// The table entry of one sub-array of a batched plan (host side).
+BatchSub batch_entry(const SubDev& d, int weight) {
+    BatchSub b{};
+    b.chans = d.chans;
+    b.cells_desc = d.cells_desc;
+    b.grp_ant = d.grp_ant;
+    b.grp_w = d.grp_w;
+    b.dft = reinterpret_cast<const uint16_t*>(d.dft16);
+    b.slots = d.slots;
+    b.C = d.C; b.A = d.A; b.V = d.C * d.KS;
+    b.N = d.N; b.KK = d.KK; b.KS = d.KS; b.NK = d.N / d.KS; b.IT = b.NK / 16; b.WAVES = d.N / 16;
+    b.NT1 = 2 / d.KS; b.WP = d.WP; b.M1max = m1max_of(d);
+    b.nibble_order = d.nibble_order; b.S = d.S; b.weight = weight; b.prog_lds = d.prog_lds;
+    return b;
+}
+
+hipError_t launch_batch(const BatchDev& bd, const uint8_t* const* samples, int n_sub, int64_t n_time,
+                        hipStream_t st) {
+    BatchArgs a{};
+    for (int s = 0; s < n_sub; ++s) a.samples[s] = samples[s];
+    a.subs = bd.table;
+    a.n_sub = n_sub;
+    a.T = n_time;
+    a.grid_wg = bd.grid_wg;
+    a.wg_per_xcd = (bd.grid_wg + 7) / 8;
+    a.lm.off_w = bd.off[0]; a.lm.off_gant = bd.off[1]; a.lm.off_desc = bd.off[2];
+    a.lm.off_smp = bd.off[3]; a.lm.off_A1 = bd.off[4]; a.lm.off_B2 = bd.off[5];
+    a.lm.smp_stride = bd.smp_stride;
+    BatchFn fn = select_batch(bd.P, bd.real != 0);
+    hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(kBatchThreads), bd.lds_bytes, st, a);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "epic_internal.hpp"
+#include "epic_sched.hpp"
 
 using namespace epic;
 
@@ -50,6 +51,18 @@ struct epic_plan_s {
     epic_status sticky = EPIC_OK;
     std::vector<void*> allocations;
     int64_t device_bytes = 0;
+    // several FP16 sub-arrays in one persistent launch
+    int batched = 0;
+    BatchDev bd{};
+    std::vector<int> weights;        // cost of one spectrum per sub-array
+    std::vector<BatchSub> table;     // host copy of bd.table
+    int autotuned = 0;
+    // hipGraph replay of one accumulate step
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t graph_T = -1;
+    std::vector<const uint8_t*> graph_ptrs;
 };
 
 namespace {
@@ -199,6 +212,10 @@ void free_all(epic_plan_s* p) {
     if (!p->dry_run) {
         hipSetDevice(p->device);
         hipDeviceSynchronize();
+        if (p->exec) hipGraphExecDestroy(p->exec);
+        if (p->graph) hipGraphDestroy(p->graph);
+        if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+        p->exec = nullptr; p->graph = nullptr; p->cap_stream = nullptr;
         for (void* v : p->allocations) hipFree(v);
     }
     p->allocations.clear();
@@ -213,6 +230,125 @@ int choose_slots(const SubDev& d, int64_t max_time) {
     int64_t S = (d.grid_wg + V - 1) / V + 1;
     S = std::max<int64_t>(1, std::min<int64_t>(S, max_time));
     return (int)S;
+}
+
+// Cost of one spectrum of one virtual channel in the batched launch, from a
+// simple model (CU cycles): MFMA instructions of both transform passes at 4
+// cycles per CU, and VALU lane operations (products, gathering, decoding) at
+// 64 per cycle.  The autotuner replaces it by measured times.
+int model_weight(const SubHost& h) {
+    const SubDev& d = h.dev;
+    const int NK = d.N / d.KS, IT = NK / 16, WAVES = d.N / 16;
+    const int R4 = (d.Rmax + 3) & ~3;
+    const double mfma = (double)WAVES * IT * d.P * 2.0 * d.KK + std::ceil(d.P * R4 / 16.0) * (2.0 * NK / 16.0) * d.KK;
+    const double entries = (double)h.grp_ant.size() / d.C;
+    const double valu = 8.0 * d.N * NK + 4.0 * d.P * entries + 2.0 * d.A * d.P;
+    return (int)std::lround(4.0 * mfma + valu / 64.0) + 1;
+}
+
+// Measure each sub-array's time per spectrum in the batched kernel, alone,
+// on all-zero input (the work does not depend on the sample values), and use
+// the ratios as the cost weights of the work split.  Each probe gives every
+// workgroup a few spectra; the time per spectrum is the slope between a
+// probe and one twice as long, which removes the launch and tail overheads.
+// The probes add into scratch slots, never into the plan's accumulators.
+epic_status autotune_batch(epic_plan_s* p, hipStream_t st) {
+    const int n_sub = (int)p->subs.size();
+    const int G = p->bd.grid_wg;
+    std::vector<double> tau(n_sub, 0.0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return EPIC_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return EPIC_E_DEVICE; }
+    epic_status rc = EPIC_OK;
+    for (int s = 0; s < n_sub && rc == EPIC_OK; ++s) {
+        const SubDev& d = p->subs[s].dev;
+        const int64_t V = (int64_t)d.C * d.KS;
+        const int64_t T1 = std::max<int64_t>(2, (2 * G + V - 1) / V), T2 = 2 * T1;
+        const int64_t S_probe = (G + V - 1) / V + 1;   // slot bound for any call length
+        uint8_t* in = nullptr;
+        float* slots = nullptr;
+        BatchSub* entry = nullptr;
+        const size_t in_bytes = (size_t)T2 * d.C * d.A * d.P;
+        const size_t slot_bytes = (size_t)S_probe * d.C * d.NPP * d.N * d.N * sizeof(float);
+        if (hipMalloc(&in, in_bytes) != hipSuccess || hipMalloc(&slots, slot_bytes) != hipSuccess ||
+            hipMalloc(&entry, sizeof(BatchSub)) != hipSuccess) {
+            rc = EPIC_E_NOMEM;
+        }
+        BatchSub probe = p->table[s];
+        probe.slots = slots;
+        probe.S = (int)S_probe;
+        if (rc == EPIC_OK && (hipMemsetAsync(in, 0, in_bytes, st) != hipSuccess ||
+                              hipMemsetAsync(slots, 0, slot_bytes, st) != hipSuccess ||
+                              hipMemcpyAsync(entry, &probe, sizeof(BatchSub), hipMemcpyHostToDevice, st) != hipSuccess))
+            rc = EPIC_E_DEVICE;
+        BatchDev one = p->bd;
+        one.table = entry;
+        const uint8_t* ptr = in;
+        double best[2] = {1e30, 1e30};
+        for (int rep = 0; rep < 8 && rc == EPIC_OK; ++rep) {
+            const int64_t Tn = (rep & 1) ? T2 : T1;
+            float ms = 0.f;
+            if (hipEventRecord(e0, st) != hipSuccess || launch_batch(one, &ptr, 1, Tn, st) != hipSuccess ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = EPIC_E_DEVICE;
+                break;
+            }
+            if (rep >= 2) best[rep & 1] = std::min(best[rep & 1], (double)ms);   // the first pair warms up
+        }
+        if (rc == EPIC_OK) {
+            const double slope = (best[1] - best[0]) / (double)(V * (T2 - T1));
+            tau[s] = slope > 0.0 ? slope : best[1] / (double)(V * T2);
+        }
+        hipStreamSynchronize(st);
+        if (entry) hipFree(entry);
+        if (slots) hipFree(slots);
+        if (in) hipFree(in);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != EPIC_OK) return rc;
+    const double tmin = *std::min_element(tau.begin(), tau.end());
+    for (int s = 0; s < n_sub; ++s)
+        p->table[s].weight = p->weights[s] = std::max(1, (int)std::lround(1000.0 * tau[s] / tmin));
+    if (hipMemcpyAsync(p->bd.table, p->table.data(), p->table.size() * sizeof(BatchSub), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return EPIC_E_DEVICE;
+    p->autotuned = 1;
+    return EPIC_OK;
+}
+
+// The kernel launches of one accumulate step.
+hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
+    if (p->batched) return launch_batch(p->bd, d_samples, (int)p->subs.size(), n_time, st);
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        const SubDev& d = p->subs[k].dev;
+        hipError_t e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
+                                                  : launch_mfma(d, d_samples[k], n_time, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Replay the step from a captured hipGraph; re-capture when the spectra
+// count or the input pointers change.
+hipError_t launch_step_graph(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
+    std::vector<const uint8_t*> ptrs(d_samples, d_samples + p->subs.size());
+    if (!p->exec || p->graph_T != n_time || p->graph_ptrs != ptrs) {
+        if (p->exec) { hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+        if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+        hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t le = launch_step(p, d_samples, n_time, p->cap_stream);
+        e = hipStreamEndCapture(p->cap_stream, &p->graph);
+        if (le != hipSuccess) return le;
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return e;
+        p->graph_T = n_time;
+        p->graph_ptrs = ptrs;
+    }
+    return hipGraphLaunch(p->exec, st);
 }
 
 epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p) {
@@ -248,14 +384,29 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cu > 0)
             p->num_cu = cu;
     }
+    for (SubHost& h : p->subs) h.dev.precision = desc->precision;
+    if (desc->precision == EPIC_FP16 && desc->n_sub > 1) {
+        // one persistent launch for every sub-array when they share a kernel family
+        std::vector<SubDev> devs;
+        for (SubHost& h : p->subs) devs.push_back(h.dev);
+        hipError_t e = batch_configure(devs.data(), (int)devs.size(), p->bd, p->dry_run ? -1 : p->device, p->num_cu);
+        if (e == hipSuccess) {
+            p->batched = 1;
+            for (size_t k = 0; k < devs.size(); ++k) p->subs[k].dev = devs[k];
+        } else if (e != hipErrorNotSupported) {
+            return hip_status(e);
+        }
+    }
     for (SubHost& h : p->subs) {
         SubDev& d = h.dev;
-        d.precision = desc->precision;
-        hipError_t e = (d.precision == EPIC_FP32) ? fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu)
-                                                  : mfma_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
-        if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
-        if (e != hipSuccess) return hip_status(e);
+        if (!p->batched) {
+            hipError_t e = (d.precision == EPIC_FP32) ? fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu)
+                                                      : mfma_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
+            if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
+            if (e != hipSuccess) return hip_status(e);
+        }
         d.S = choose_slots(d, desc->max_time);
+        p->weights.push_back(p->batched ? model_weight(h) : 1);
         // size checks (also in dry run)
         const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
         if (slot_bytes > 64.0 * (1ull << 30)) return EPIC_E_NOMEM;
@@ -299,6 +450,22 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if ((s = hip_status(launch_dft_matrix(d, st))) != EPIC_OK) return s;
         }
         if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
+    }
+    if (p->batched) {
+        p->table.clear();
+        for (size_t k = 0; k < p->subs.size(); ++k) p->table.push_back(batch_entry(p->subs[k].dev, p->weights[k]));
+        epic_status s = dalloc(p, &p->bd.table, p->table.size());
+        if (s != EPIC_OK) return s;
+        if ((s = hip_status(hipMemcpyAsync(p->bd.table, p->table.data(), p->table.size() * sizeof(BatchSub),
+                                           hipMemcpyHostToDevice, st))) != EPIC_OK)
+            return s;
+        if (desc->flags & EPIC_F_AUTOTUNE) {
+            if ((s = autotune_batch(p, st)) != EPIC_OK) return s;
+        }
+    }
+    if (desc->flags & EPIC_F_GRAPH) {
+        hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_status(e);
     }
     return hip_status(hipStreamSynchronize(st));
 }
@@ -352,7 +519,7 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
     }
     if (desc->precision == EPIC_FP8) return EPIC_E_UNSUPPORTED;
     if (desc->gridder != EPIC_GRID_AUTO && desc->gridder != EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
-    if (desc->flags & (EPIC_F_REMOVE_AUTOCORR | EPIC_F_GRAPH | EPIC_F_AUTOTUNE)) return EPIC_E_UNSUPPORTED;
+    if (desc->flags & EPIC_F_REMOVE_AUTOCORR) return EPIC_E_UNSUPPORTED;
     epic_plan_s* p = new (std::nothrow) epic_plan_s();
     if (!p) return EPIC_E_NOMEM;
     epic_status s;
@@ -383,13 +550,9 @@ epic_status epic_grid_fft_accumulate(epic_plan_t p, const uint8_t* const* d_samp
         if (!d_samples[k]) return EPIC_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
-    for (size_t k = 0; k < p->subs.size(); ++k) {
-        const SubDev& d = p->subs[k].dev;
-        hipError_t e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
-                                                  : launch_mfma(d, d_samples[k], n_time, st);
-        if (e != hipSuccess) return check_device(p, e);
-    }
-    return EPIC_OK;
+    hipError_t e = (p->desc.flags & EPIC_F_GRAPH) ? launch_step_graph(p, d_samples, n_time, st)
+                                                  : launch_step(p, d_samples, n_time, st);
+    return check_device(p, e);
 }
 
 epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, void* hip_stream) {
@@ -430,6 +593,62 @@ epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
         info->lds_bytes[k] = (int64_t)d.lds_bytes;
     }
     info->device_bytes = p->device_bytes;
+    info->graph = (p->desc.flags & EPIC_F_GRAPH) ? 1 : 0;
+    info->autotuned = p->autotuned;
+    info->batched = p->batched;
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        info->weight[k] = p->weights[k];
+        info->col_split[k] = p->subs[k].dev.KS;
+        info->workgroups[k] = p->subs[k].dev.grid_wg;
+    }
+    return EPIC_OK;
+}
+
+epic_status epic_debug_schedule(epic_plan_t p, int32_t sub, int64_t n_time, int32_t* h_wg, int32_t* h_slot) {
+    if (!valid_plan(p) || !h_wg || !h_slot || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
+    if (n_time < 1 || n_time > p->desc.max_time) return EPIC_E_ARG;
+    const SubDev& d = p->subs[sub].dev;
+    const int64_t n = (int64_t)d.C * d.KS * n_time;
+    std::fill(h_wg, h_wg + n, -1);
+    std::fill(h_slot, h_slot + n, -1);
+    // the launch that holds `sub`: all sub-arrays (batched) or this one alone
+    std::vector<int> members;
+    if (p->batched) {
+        for (int s = 0; s < (int)p->subs.size(); ++s) members.push_back(s);
+    } else {
+        members.push_back(sub);
+    }
+    int64_t total = 0;
+    for (int s : members) total += (int64_t)p->subs[s].dev.C * p->subs[s].dev.KS * n_time * p->weights[s];
+    const int G = d.grid_wg;
+    const int64_t Lc = (total + G - 1) / G;
+    for (int g = 0; g < G; ++g) {
+        int64_t base = 0;
+        for (int s : members) {
+            const SubDev& e = p->subs[s].dev;
+            const int64_t items = (int64_t)e.C * e.KS * n_time, w = p->weights[s];
+            int64_t k0, k1;
+            owned_range(g, Lc, base, w, items, &k0, &k1);
+            if (s == sub) {
+                // the kernels' segment walk: one piece per virtual channel
+                for (int64_t f = k0; f < k1;) {
+                    const int64_t v = f / n_time, t = f - v * n_time;
+                    const int64_t len = std::min(k1 - f, n_time - t);
+                    const int slot = slot_of(g, v, t, n_time, base, w, Lc);
+                    if (slot < 0 || slot >= d.S) return EPIC_E_STATE;
+                    for (int64_t k = f; k < f + len; ++k) {
+                        if (h_wg[k] != -1) return EPIC_E_STATE;
+                        h_wg[k] = g;
+                        h_slot[k] = slot;
+                    }
+                    f += len;
+                }
+            }
+            base += items * w;
+        }
+    }
+    for (int64_t k = 0; k < n; ++k)
+        if (h_wg[k] < 0) return EPIC_E_STATE;
     return EPIC_OK;
 }
 

@@ -60,7 +60,9 @@ class epic_plan_info(ctypes.Structure):
                 ("output", ctypes.c_int32), ("npp", ctypes.c_int32 * 16), ("slots", ctypes.c_int32 * 16),
                 ("window_max", ctypes.c_int32 * 16), ("threads", ctypes.c_int32 * 16),
                 ("device_bytes", ctypes.c_int64), ("lds_bytes", ctypes.c_int64 * 16),
-                ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32), ("batched", ctypes.c_int32),
+                ("weight", ctypes.c_int32 * 16), ("col_split", ctypes.c_int32 * 16),
+                ("workgroups", ctypes.c_int32 * 16)]
 
 
 _P = ctypes.POINTER
@@ -71,17 +73,19 @@ _lib.epic_readout.argtypes = [_vp, _P(_vp), ctypes.c_int32, _vp]
 _lib.epic_set_gains.argtypes = [_vp, ctypes.c_int32, _P(ctypes.c_float), _vp]
 _lib.epic_plan_query.argtypes = [_vp, _P(epic_plan_info)]
 _lib.epic_debug_geometry.argtypes = [_vp, ctypes.c_int32, _P(ctypes.c_int32)]
+_lib.epic_debug_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, _P(ctypes.c_int32), _P(ctypes.c_int32)]
 _lib.epic_debug_unpack.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp]
 _lib.epic_destroy.argtypes = [_vp]
 _lib.epic_status_str.argtypes = [ctypes.c_int]
 _lib.epic_status_str.restype = ctypes.c_char_p
 _lib.epic_abi_version.argtypes = []
 for _f in ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_plan_query",
-           "epic_debug_geometry", "epic_debug_unpack", "epic_destroy", "epic_abi_version"):
+           "epic_debug_geometry", "epic_debug_schedule", "epic_debug_unpack", "epic_destroy", "epic_abi_version"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_plan_query",
-            "epic_debug_geometry", "epic_debug_unpack", "epic_destroy", "epic_status_str", "epic_abi_version")
+            "epic_debug_geometry", "epic_debug_schedule", "epic_debug_unpack", "epic_destroy", "epic_status_str",
+            "epic_abi_version")
 
 
 def library_path() -> str:
@@ -215,7 +219,23 @@ def epic_plan_query(plan: Plan) -> dict:
     return {"n_sub": n, "precision": info.precision, "gridder": info.gridder, "output": info.output,
             "npp": list(info.npp[:n]), "slots": list(info.slots[:n]), "window_max": list(info.window_max[:n]),
             "threads": list(info.threads[:n]), "device_bytes": int(info.device_bytes),
-            "lds_bytes": list(info.lds_bytes[:n]), "graph": info.graph, "autotuned": info.autotuned}
+            "lds_bytes": list(info.lds_bytes[:n]), "graph": info.graph, "autotuned": info.autotuned,
+            "batched": info.batched, "weight": list(info.weight[:n]), "col_split": list(info.col_split[:n]),
+            "workgroups": list(info.workgroups[:n])}
+
+
+def epic_debug_schedule(plan: Plan, sub: int, n_time: int):
+    """Owner workgroup and slot of every spectrum of sub-array ``sub`` in an
+    accumulate call of ``n_time`` spectra: two int32 arrays [C * KS][n_time]."""
+    if not 0 <= int(sub) < len(plan.subs) or int(n_time) < 1:   # let the library reject it
+        _check(_lib.epic_debug_schedule(plan, int(sub), int(n_time), None, None), "epic_debug_schedule")
+    info = epic_plan_query(plan)
+    V = plan.subs[sub].n_chan * info["col_split"][sub]
+    wg = np.empty((V, int(n_time)), dtype=np.int32)
+    slot = np.empty_like(wg)
+    _check(_lib.epic_debug_schedule(plan, int(sub), int(n_time), wg.ctypes.data_as(_P(ctypes.c_int32)),
+                                    slot.ctypes.data_as(_P(ctypes.c_int32))), "epic_debug_schedule")
+    return wg, slot
 
 
 def epic_debug_geometry(plan: Plan, sub: int) -> np.ndarray:

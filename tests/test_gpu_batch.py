@@ -1,0 +1,168 @@
+"""GPU parity of several sub-arrays of unequal size imaged in one persistent
+launch (FP16 matrix-core form), of the plan-time autotuner that sets the work
+split from measured times, and of hipGraph replay of the accumulate step.
+
+Tolerances: 1e-3 per image against the FP64 oracle (the reduced-precision
+bar, as for one sub-array); a batched plan and separate one-sub-array plans
+compute every spectrum with the same arithmetic and differ only in how the
+time sum is split into partial slots, so they agree to FP32 summation
+rounding (1e-5).  A graph replay runs the same kernels with the same
+arguments as the eager call, so its result is bit-identical.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_parity, image_errors, run_library, torch_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2301_09662_amd import epic
+    return epic
+
+
+def uneven(nchan=(3, 2, 2), T=10, seed_t0=0):
+    """The three sub-arrays of the uneven batch (256 ant at N=64, 128 ant at
+    N=48, 512 ant at N=96) with fewer channels."""
+    subs = [synth.shrink(s, n_chan=n) for s, n in zip(synth.workload(4).subs, nchan)]
+    return subs, [synth.samples(s, T, seed_t0) for s in subs]
+
+
+def test_split_of_device_plans(E):
+    """The work split with the device's real workgroup count, checked on the
+    host before any batched kernel runs: one owner per spectrum, slots in
+    range and distinct per channel (epic_debug_schedule reports a violation
+    as an error)."""
+    for nchan, T in (((3, 2, 2), 10), ((2, 2, 1), 9), ((2, 1, 1), 7), ((1, 1, 1), 3), ((132, 64, 32), 250)):
+        subs = [synth.shrink(s, n_chan=n) for s, n in zip(synth.workload(4).subs, nchan)]
+        plan = E.epic_plan(subs, precision="fp16", max_time=T)
+        try:
+            info = E.epic_plan_query(plan)
+            for k in range(3):
+                for n in sorted({1, 2, T // 2 or 1, T}):
+                    wg, slot = E.epic_debug_schedule(plan, k, n)
+                    assert (slot < info["slots"][k]).all()
+        finally:
+            E.epic_destroy(plan)
+
+
+def test_batched_parity(E):
+    subs, xs = uneven()
+    gpu, info = run_library(E, subs, xs, precision="fp16")
+    assert info["batched"] == 1 and info["n_sub"] == 3
+    assert all(w >= 1 for w in info["weight"])
+    for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
+        fro, mx = assert_parity(g, oracle.image(s, x), TOL, f"batched sub {k}")
+        print(f"batched sub {k} (A={s.n_ant}, N={s.grid_n}): rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+
+
+def test_batched_matches_separate_plans(E):
+    subs, xs = uneven(nchan=(2, 2, 1), T=9)
+    batched, _ = run_library(E, subs, xs, precision="fp16")
+    for k, (s, x) in enumerate(zip(subs, xs)):
+        (alone,), info = run_library(E, [s], [x], precision="fp16")
+        assert info["batched"] == 0
+        fro, mx = image_errors(batched[k], alone)
+        assert fro.max() <= 1e-5 and mx.max() <= 1e-5, f"sub {k}: {fro.max():.2e} {mx.max():.2e}"
+
+
+def test_batched_split_calls_and_single_spectrum(E):
+    subs, xs = uneven(nchan=(2, 1, 1), T=7)
+    gpu, _ = run_library(E, subs, xs, precision="fp16", calls=[1, 4, 2])
+    for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
+        assert_parity(g, oracle.image(s, x), TOL, f"split calls sub {k}")
+
+
+def test_autotuned_split(E):
+    subs, xs = uneven(nchan=(2, 2, 2), T=12)
+    gpu, info = run_library(E, subs, xs, precision="fp16", flags=E.EPIC_F_AUTOTUNE)
+    assert info["batched"] == 1 and info["autotuned"] == 1
+    w = info["weight"]
+    print("autotuned weights per spectrum (A, B, C):", w)
+    assert min(w) >= 1 and min(w) == 1000   # measured times relative to the cheapest sub-array
+    for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
+        assert_parity(g, oracle.image(s, x), TOL, f"autotuned sub {k}")
+
+
+def test_mixed_pol_counts_run_separately(E):
+    """Sub-arrays of different polarisation counts cannot share the batched
+    kernel: the plan falls back to one launch per sub-array."""
+    a = synth.shrink(synth.workload(4).subs[1], n_chan=2)
+    b = synth.shrink(synth.workload(1).subs[0], n_chan=2)
+    xs = [synth.samples(a, 6), synth.samples(b, 6)]
+    gpu, info = run_library(E, [a, b], xs, precision="fp16")
+    assert info["batched"] == 0
+    for k, (s, x, g) in enumerate(zip([a, b], xs, gpu)):
+        assert_parity(g, oracle.image(s, x), TOL, f"mixed sub {k}")
+
+
+def test_full_uneven_batch_sampled_channels(E):
+    """The full uneven batch (132 / 64 / 32 channels, 250 spectra, one call,
+    autotuned) against the oracle on the first and last channel of each
+    sub-array."""
+    wl = synth.workload(4)
+    xs = [synth.samples(s, wl.n_time) for s in wl.subs]
+    gpu, info = run_library(E, wl.subs, xs, precision="fp16", flags=E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH)
+    assert info["batched"] == 1 and info["graph"] == 1
+    for k, (s, x, g) in enumerate(zip(wl.subs, xs, gpu)):
+        for c in (0, s.n_chan - 1):
+            ora = oracle.image(s, x, chans=range(c, c + 1))
+            fro, mx = assert_parity(g[c:c + 1], ora[c:c + 1], TOL, f"full batch sub {k} channel {c}")
+            print(f"full batch sub {k} channel {c}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+
+
+def _graph_vs_eager(E, subs, xs, precision, n_list):
+    """Run the same accumulate / readout sequence through an eager plan and a
+    graph plan, with unrelated torch work between replays, and return both
+    lists of read-out cubes."""
+    torch, dev = torch_dev()
+    d = [torch.from_numpy(x).to(dev) for x in xs]
+    T = xs[0].shape[0]
+    res = {}
+    for flags in (0, E.EPIC_F_GRAPH):
+        plan = E.epic_plan(subs, precision=precision, max_time=T, flags=flags)
+        try:
+            info = E.epic_plan_query(plan)
+            assert info["graph"] == (1 if flags else 0)
+            outs = []
+            for n in n_list:
+                o = [torch.zeros((s.n_chan, info["npp"][k], s.grid_n, s.grid_n), dtype=torch.float32, device=dev)
+                     for k, s in enumerate(subs)]
+                E.epic_grid_fft_accumulate(plan, [x[:n] for x in d], n)
+                junk = torch.randn(1 << 20, device=dev)       # eager work between replays
+                junk.mul_(2.0).sum().item()
+                E.epic_readout(plan, o, 1)
+                torch.cuda.synchronize()
+                outs.append([t.cpu().numpy() for t in o])
+            res[flags] = outs
+        finally:
+            E.epic_destroy(plan)
+    return res[0], res[E.EPIC_F_GRAPH]
+
+
+def test_graph_replay_batched_fp16(E):
+    subs, xs = uneven(nchan=(2, 1, 1), T=8)
+    # replays of one capture, then a different n_time (re-capture), then the first again
+    eager, graph = _graph_vs_eager(E, subs, xs, "fp16", [8, 8, 8, 5, 8])
+    for r, (a, b) in enumerate(zip(eager, graph)):
+        for k in range(len(subs)):
+            assert np.array_equal(a[k], b[k]), f"replay {r} sub {k} differs from the eager result"
+    assert_parity(graph[0][0].astype(np.float64), oracle.image(subs[0], xs[0]), TOL, "graph batched")
+
+
+def test_graph_replay_fp32_two_subs(E):
+    """FP32 with two sub-arrays: the graph holds one launch per sub-array."""
+    a = synth.shrink(synth.workload(1).subs[0], n_chan=3)
+    b = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=64)
+    xs = [synth.samples(a, 9), synth.samples(b, 9)]
+    eager, graph = _graph_vs_eager(E, [a, b], xs, "fp32", [9, 9, 4, 9])
+    for r, (x, y) in enumerate(zip(eager, graph)):
+        for k in range(2):
+            assert np.array_equal(x[k], y[k]), f"replay {r} sub {k}"
+    for k, (s, x) in enumerate(zip([a, b], xs)):
+        assert_parity(graph[0][k].astype(np.float64), oracle.image(s, x), 1e-5, f"graph fp32 sub {k}")

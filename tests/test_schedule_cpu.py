@@ -1,0 +1,102 @@
+"""The work split of the persistent launches, checked on the host through
+epic_debug_schedule (the same split and slot functions the kernels run):
+every spectrum has exactly one owner workgroup, a workgroup's spectra of one
+virtual channel are contiguous in time, its slot is inside the plan's slot
+count, and two workgroups never add into the same slot of one channel (the
+partial sums need no atomics).  Covers one-sub-array FP32 and FP16 plans and
+the batched FP16 plan of sub-arrays of unequal cost, including calls so short
+that one spectrum costs more than a workgroup's share."""
+import numpy as np
+import pytest
+
+import synth
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2301_09662_amd import epic
+    return epic
+
+
+def check_split(E, plan, sub, n_time):
+    info = E.epic_plan_query(plan)
+    wg, slot = E.epic_debug_schedule(plan, sub, n_time)
+    S = info["slots"][sub]
+    assert (wg >= 0).all() and (wg < info["workgroups"][sub]).all()
+    assert (slot >= 0).all() and (slot < S).all()
+    for v in range(wg.shape[0]):
+        owners, first = np.unique(wg[v], return_index=True)
+        # contiguous pieces: the owner changes exactly len(owners) - 1 times
+        assert np.count_nonzero(np.diff(wg[v])) == len(owners) - 1
+        # one slot per owner, distinct across owners
+        s_of = slot[v][first]
+        assert len(np.unique(s_of)) == len(owners)
+        for o, s in zip(owners, s_of):
+            assert (slot[v][wg[v] == o] == s).all()
+    return wg, slot
+
+
+def dry(E, subs, precision, max_time, flags=0):
+    return E.epic_plan(subs, precision=precision, max_time=max_time, flags=E.EPIC_F_DRY_RUN | flags)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("n_time", [1, 2, 7, 999, 1000])
+def test_station_split(E, precision, n_time):
+    p = dry(E, synth.workload(2).subs, precision, 1000)
+    try:
+        check_split(E, p, 0, n_time)
+    finally:
+        E.epic_destroy(p)
+
+
+@pytest.mark.parametrize("n_time", [1, 2, 3, 5, 17, 250])
+def test_uneven_batch_split(E, n_time):
+    wl = synth.workload(4)
+    p = dry(E, wl.subs, "fp16", wl.n_time)
+    try:
+        info = E.epic_plan_query(p)
+        assert info["batched"] == 1 and min(info["weight"]) >= 1
+        # the N=96 array has the most expensive spectra in the cost model
+        assert info["weight"][2] == max(info["weight"])
+        for k in range(3):
+            check_split(E, p, k, n_time)
+    finally:
+        E.epic_destroy(p)
+
+
+def test_heavy_spectra_get_one_owner_each(E):
+    """A batch with one channel per sub-array and short calls: a spectrum
+    costs more than a workgroup's share, so each has its own owner and the
+    slot is the spectrum index, which must stay below the slot count even
+    where max_time caps it."""
+    subs = [synth.shrink(s, n_chan=1) for s in synth.workload(4).subs]
+    p = dry(E, subs, "fp16", 3)
+    try:
+        info = E.epic_plan_query(p)
+        assert info["batched"] == 1 and max(info["slots"]) <= 3
+        G = info["workgroups"][0]
+        for n_time in (1, 2, 3):
+            total = sum(s.n_chan * info["col_split"][k] * n_time * info["weight"][k] for k, s in enumerate(subs))
+            Lc = -(-total // G)
+            heavy = [k for k in range(3) if info["weight"][k] >= Lc]
+            assert heavy, "no sub-array in the one-owner-per-spectrum regime"
+            for k in range(3):
+                wg, slot = check_split(E, p, k, n_time)
+                if k in heavy:
+                    assert len(np.unique(wg)) == wg.size
+                    assert (slot == np.arange(n_time)[None, :]).all()
+    finally:
+        E.epic_destroy(p)
+
+
+def test_schedule_validates(E):
+    p = dry(E, synth.workload(1).subs, "fp32", 10)
+    try:
+        for bad in (0, 11, -1):
+            with pytest.raises(E.EpicError):
+                E.epic_debug_schedule(p, 0, bad)
+        with pytest.raises(E.EpicError):
+            E.epic_debug_schedule(p, 1, 5)
+    finally:
+        E.epic_destroy(p)
