@@ -44,6 +44,37 @@ def algorithmic_flops_per_ct(sub) -> float:
     return grid + fft + prod
 
 
+# Sources of each precision's hot kernel: the counter-based traffic in
+# profiles/traffic.json is reported only while their hash still matches.
+KERNEL_SOURCES = {
+    "fp32": ["kernels_fp32.hip", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp", "epic_internal.hpp"],
+    "fp16": ["kernels_mfma.hip", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp", "epic_internal.hpp"],
+}
+
+
+def sources_sha256(precision):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(precision, []):
+        with open(os.path.join(ROOT, "paper_2301_09662_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(precision, workload):
+    """HBM bytes per launch of the hot kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by the plain-copy calibration), or None
+    when there are none for this workload or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        entry = json.load(fh).get("kernels", {}).get(f"{precision}:{workload}")
+    if not entry or entry.get("sources_sha256") != sources_sha256(precision):
+        return None
+    return entry["bytes_per_launch"]
+
+
 def cpu_baseline(sub, samples, budget_s=15.0):
     """Time the FP64 oracle on a bounded sample of the same workload: all
     channels over the first T_s spectra, T_s sized for ~budget_s of wall time."""
@@ -72,8 +103,9 @@ def main():
     ap.add_argument("--cfg", type=int, default=2, help="workload config (default: station FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP16 matrix-core leg")
-    ap.add_argument("--precision", choices=["fp32", "fp16"], default=None,
-                    help="override the workload's precision (station: fp32; uneven batch: fp16)")
+    ap.add_argument("--precision", choices=["fp32", "fp16", "fp8"], default=None,
+                    help="override the workload's own precision")
+    ap.add_argument("--no-graph", action="store_true", help="batched workloads: eager launches, no autotuning")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE hardware counters")
@@ -133,10 +165,10 @@ def main():
         E.epic_destroy(plan)
         return wall / steps * 1e3, kern_ms, [o.double().cpu().numpy() for o in outs], info
 
-    # the uneven batch of sub-arrays runs as one autotuned persistent FP16
-    # launch replayed from a hipGraph; the station workloads in FP32
-    precision = args.precision or ("fp16" if len(subs) > 1 else "fp32")
-    flags = (E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH) if len(subs) > 1 else 0
+    # each workload's own precision; the uneven batch of sub-arrays runs as
+    # one autotuned persistent launch replayed from a hipGraph
+    precision = args.precision or wl.precision
+    flags = (E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH) if len(subs) > 1 and not args.no_graph else 0
     ms_per_step, kern_ms, img32, info32 = run(precision, args.steps, args.warmup, flags)
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
     res = {
@@ -157,7 +189,7 @@ def main():
             + f", T={T} spectra per step", "n_time": T, "precision": precision,
             "plan": {k: info32[k] for k in ("batched", "autotuned", "graph", "weight", "slots", "lds_bytes")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": counter_traffic(precision, wl.name),
                      "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch,
                      "frac_of_nonpacked_issue": achieved / FP32_NONPACKED_TFLOPS},
     }

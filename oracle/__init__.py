@@ -67,9 +67,10 @@ def _load():
         lib.ora_dft2.argtypes = [ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
         lib.ora_image_range.argtypes = [P(_OraArray), P(ctypes.c_uint8), ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_int, P(ctypes.c_double), ctypes.c_int]
+        lib.ora_autocorr_range.argtypes = lib.ora_image_range.argtypes
         lib.ora_max_threads.argtypes = []
         for f in ("ora_unpack_table", "ora_geometry", "ora_taps", "ora_grid", "ora_dft2",
-                  "ora_image_range", "ora_max_threads"):
+                  "ora_image_range", "ora_autocorr_range", "ora_max_threads"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -185,10 +186,26 @@ def dft2(x: np.ndarray) -> np.ndarray:
     return out[..., 0] + 1j * out[..., 1]
 
 
-def image(sub, samples: np.ndarray, chans: Optional[range] = None, n_threads: int = 0, **kw) -> np.ndarray:
+def image(sub, samples: np.ndarray, chans: Optional[range] = None, n_threads: int = 0,
+          remove_autocorr: bool = False, **kw) -> np.ndarray:
     """FP64 image cube [C][NPP][N][N] (products XX*, YY*, Re XY*, Im XY*; single
     pol: XX*), summed over all T spectra of ``samples`` (uint8 [T][C][A][P]).
-    ``chans`` restricts the channels computed (others are returned as zero)."""
+    ``chans`` restricts the channels computed (others are returned as zero).
+    ``remove_autocorr`` subtracts every antenna's own (a = b) contribution,
+    which autocorr() returns."""
+    out = _run("ora_image_range", sub, samples, chans, n_threads, **kw)
+    if remove_autocorr:
+        out -= _run("ora_autocorr_range", sub, samples, chans, n_threads, **kw)
+    return out
+
+
+def autocorr(sub, samples: np.ndarray, chans: Optional[range] = None, n_threads: int = 0, **kw) -> np.ndarray:
+    """FP64 [C][NPP][N][N]: the a = b terms of the image, sum over antennas of
+    K^p_a K^q_a^* sum_t E^p_a E^q_a^* (K^p_a: antenna a's kernel transformed alone)."""
+    return _run("ora_autocorr_range", sub, samples, chans, n_threads, **kw)
+
+
+def _run(fn, sub, samples, chans, n_threads, **kw):
     s = _spec(sub, **kw)
     lib = _load()
     samples = np.ascontiguousarray(samples, dtype=np.uint8)
@@ -199,10 +216,10 @@ def image(sub, samples: np.ndarray, chans: Optional[range] = None, n_threads: in
     out = np.zeros((s.n_chan, s.npp, N, N), dtype=np.float64)
     c0, c1 = (0, s.n_chan) if chans is None else (chans.start, chans.stop)
     st = s.c_struct()
-    rc = lib.ora_image_range(ctypes.byref(st), _ptr(samples, ctypes.c_uint8), int(T), int(c0), int(c1),
-                             _ptr(out, ctypes.c_double), int(n_threads))
+    rc = getattr(lib, fn)(ctypes.byref(st), _ptr(samples, ctypes.c_uint8), int(T), int(c0), int(c1),
+                          _ptr(out, ctypes.c_double), int(n_threads))
     if rc:
-        raise OracleError(rc, "image")
+        raise OracleError(rc, fn)
     return out
 
 

@@ -276,6 +276,110 @@ int ora_image_range(const ora_array* s, const uint8_t* samples, int64_t T,
     return nomem ? ORA_E_NOMEM : ORA_OK;
 }
 
+/* ---- the a = b terms of step 4: autocorrelation image ------------------ */
+/*
+ * The image of Eq. 4 is a sum over antenna pairs (a, b) (Eq. 3); this returns
+ * only the pairs a = b, i.e. for every antenna its own contribution
+ *   sum_t (K^p_a E^p_a(t)) (K^q_a E^q_a(t))^*  =  K^p_a K^q_a^*  sum_t E^p_a E^q_a^*
+ * where K^p_a(i, j) is antenna a's kernel (with the (-1)^(x+y) factor)
+ * transformed on its own, sum over taps of w (-1)^(x+y) exp(+2 pi i (x i + y j)/N).
+ * The image with the autocorrelations removed is the full image minus this.
+ * Same layout, channel range and threading as ora_image_range.
+ */
+int ora_autocorr_range(const ora_array* s, const uint8_t* samples, int64_t T,
+                       int chan_begin, int chan_end, double* out, int n_threads) {
+    int rc = check_array(s);
+    if (rc) return rc;
+    if (!samples || !out || T < 0) return ORA_E_ARG;
+    if (chan_begin < 0 || chan_end > s->n_chan || chan_begin > chan_end) return ORA_E_ARG;
+    const int N = s->grid_n, A = s->n_ant, P = s->n_pol, C = s->n_chan, K = s->kernel_k, h = K / 2;
+    const int NPP = (P == 2) ? 4 : 1;
+    const size_t NN = (size_t)N * N;
+
+    int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * (size_t)C * A * 2);
+    double* g = (double*)malloc(sizeof(double) * (size_t)C * A * 2);
+    double* taps = (double*)malloc(sizeof(double) * (size_t)C * A * P * K * K * 2);
+    double* tw = (double*)malloc(sizeof(double) * 2 * N);
+    if (!cell || !g || !taps || !tw) { free(cell); free(g); free(taps); free(tw); return ORA_E_NOMEM; }
+    rc = ora_geometry(s, cell, g);
+    if (rc == ORA_OK) rc = ora_taps(s, cell, g, taps);
+    if (rc != ORA_OK) { free(cell); free(g); free(taps); free(tw); return rc; }
+    twiddle_table(N, tw);
+
+    int nomem = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+#endif
+    for (int c = chan_begin; c < chan_end; ++c) {
+        double* kimg = (double*)malloc(sizeof(double) * 2 * NN * P);
+        if (!kimg) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            nomem = 1;
+            continue;
+        }
+        double* acc = out + (size_t)c * NPP * NN;
+        memset(acc, 0, sizeof(double) * NPP * NN);
+        const double* taps_c = taps + (size_t)c * A * P * K * K * 2;
+        const int32_t* cell_c = cell + (size_t)c * A * 2;
+        for (int a = 0; a < A; ++a) {
+            /* the antenna's zero-lag correlations over the call: XX*, YY*, XY* */
+            double vxx = 0.0, vyy = 0.0, vxyr = 0.0, vxyi = 0.0;
+            for (int64_t t = 0; t < T; ++t) {
+                const uint8_t* row = samples + ((size_t)t * C + c) * (size_t)A * P;
+                double xr, xi;
+                unpack(row[a * P], s->nibble_order, &xr, &xi);
+                vxx += xr * xr + xi * xi;
+                if (P == 2) {
+                    double yr, yi;
+                    unpack(row[a * P + 1], s->nibble_order, &yr, &yi);
+                    vyy += yr * yr + yi * yi;
+                    vxyr += xr * yr + xi * yi;
+                    vxyi += xi * yr - xr * yi;
+                }
+            }
+            /* the antenna's kernel transform per polarisation */
+            for (int p = 0; p < P; ++p) {
+                const double* w = taps_c + ((size_t)a * P + p) * K * K * 2;
+                double* kp = kimg + (size_t)p * 2 * NN;
+                for (int j = 0; j < N; ++j)
+                    for (int i = 0; i < N; ++i) {
+                        double kr = 0.0, ki = 0.0;
+                        for (int dy = -h; dy <= h; ++dy)
+                            for (int dx = -h; dx <= h; ++dx) {
+                                int x = cell_c[2 * a + 0] + dx, y = cell_c[2 * a + 1] + dy;
+                                double sgn = ((x + y) & 1) ? -1.0 : 1.0;
+                                double wr = sgn * w[((dy + h) * K + (dx + h)) * 2 + 0];
+                                double wi = sgn * w[((dy + h) * K + (dx + h)) * 2 + 1];
+                                const double* e = tw + 2 * (((long)x * i + (long)y * j) % N);
+                                kr += wr * e[0] - wi * e[1];
+                                ki += wr * e[1] + wi * e[0];
+                            }
+                        kp[(j * N + i) * 2] = kr;
+                        kp[(j * N + i) * 2 + 1] = ki;
+                    }
+            }
+            for (size_t q = 0; q < NN; ++q) {
+                double ar = kimg[2 * q], ai = kimg[2 * q + 1];
+                acc[q] += vxx * (ar * ar + ai * ai);                         /* XX* */
+                if (P == 2) {
+                    double br = kimg[2 * NN + 2 * q], bi = kimg[2 * NN + 2 * q + 1];
+                    acc[NN + q] += vyy * (br * br + bi * bi);                /* YY* */
+                    /* K^X K^Y* times the correlation X Y* */
+                    double kr = ar * br + ai * bi, ki = ai * br - ar * bi;
+                    acc[2 * NN + q] += vxyr * kr - vxyi * ki;                /* Re X Y* */
+                    acc[3 * NN + q] += vxyr * ki + vxyi * kr;                /* Im X Y* */
+                }
+            }
+        }
+        free(kimg);
+    }
+    free(cell); free(g); free(taps); free(tw);
+    return nomem ? ORA_E_NOMEM : ORA_OK;
+}
+
 int ora_image(const ora_array* s, const uint8_t* samples, int64_t T, double* out, int n_threads) {
     if (!s) return ORA_E_ARG;
     return ora_image_range(s, samples, T, 0, s->n_chan, out, n_threads);

@@ -43,8 +43,9 @@ def kernel_images(cell_c: np.ndarray, taps_c: np.ndarray, N: int) -> np.ndarray:
 
 
 def fx_image(samples: np.ndarray, cell: np.ndarray, taps: np.ndarray, N: int,
-             chans=None, nibble_order: int = 0) -> np.ndarray:
-    """FP64 [C][NPP][N][N] image via visibilities and direct per-pixel imaging."""
+             chans=None, nibble_order: int = 0, drop_auto: bool = False) -> np.ndarray:
+    """FP64 [C][NPP][N][N] image via visibilities and direct per-pixel imaging.
+    ``drop_auto`` leaves out the a = b baselines (each antenna with itself)."""
     T, C, A, P = samples.shape
     npp = 4 if P == 2 else 1
     chans = range(C) if chans is None else chans
@@ -56,6 +57,8 @@ def fx_image(samples: np.ndarray, cell: np.ndarray, taps: np.ndarray, N: int,
         Kc = kernel_images(cell[c], taps[c], N).reshape(A, P, N * N)
         def img(p, q):
             V = np.einsum("ta,tb->ab", e[:, :, p], np.conj(e[:, :, q]))   # Eq. 1
+            if drop_auto:
+                np.fill_diagonal(V, 0)
             M = V @ np.conj(Kc[:, q])                                      # [a][pix]
             return np.einsum("ap,ap->p", Kc[:, p], M).reshape(N, N)
         xx = img(0, 0)

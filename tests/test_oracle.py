@@ -195,6 +195,43 @@ def test_fx_identity_dual_pol_user_taps():
     assert np.abs(img - ref).max() <= 1e-12 * scale
 
 
+def test_autocorr_removed_is_fx_without_diagonal():
+    """Image with the autocorrelations removed == FX imaging of the a != b
+    baselines only (dual pol, complex per-pol user taps)."""
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=40)
+    x = synth.samples(sub, 20)
+    rng = np.random.default_rng(6)
+    t = rng.standard_normal((2, 40, 2, 3, 3, 2)).astype(np.float32)
+    img = oracle.image(sub, x, taps=t, remove_autocorr=True)
+    cell, _ = oracle.geometry(sub)
+    ref = fx_image(x, cell, oracle.taps(sub, taps=t), sub.grid_n, drop_auto=True)
+    full = fx_image(x, cell, oracle.taps(sub, taps=t), sub.grid_n)
+    scale = np.sqrt(np.abs(full[:, 0]).max() * np.abs(full[:, 1]).max())
+    assert np.abs(img - ref).max() <= 1e-12 * scale
+
+
+def test_autocorr_is_sum_of_single_antenna_images():
+    """The a = b image equals the sum of the images of one-antenna arrays
+    (each antenna keeps its own cell and taps), by the main imaging route."""
+    import copy
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=6)
+    x = synth.samples(sub, 16)
+    au = oracle.autocorr(sub, x)
+    tot = np.zeros_like(au)
+    for a in range(sub.n_ant):
+        one = copy.copy(sub)
+        one.ant_xy = sub.ant_xy[a:a + 1]   # n_ant follows ant_xy
+        tot += oracle.image(one, np.ascontiguousarray(x[:, :, a:a + 1]))
+    assert np.abs(au - tot).max() <= 1e-12 * np.abs(tot).max()
+    # the single-pol tiny configuration too
+    sub1 = synth.workload(1).subs[0]
+    x1 = synth.samples(sub1, 32)
+    cell, _ = oracle.geometry(sub1)
+    ref = fx_image(x1, cell, oracle.taps(sub1), sub1.grid_n) - fx_image(x1, cell, oracle.taps(sub1), sub1.grid_n,
+                                                                          drop_auto=True)
+    assert np.abs(oracle.autocorr(sub1, x1) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_parseval():
     """sum_pixels XX* = N^2 sum_t sum_cells |G_X|^2, and the same for X Y*."""
     sub = synth.shrink(synth.workload(2).subs[0], n_chan=1, n_ant=40)
@@ -279,7 +316,16 @@ MUTANTS = {
     # nibble order swapped
     "nibble": ("if (order == 0) { *re = hi; *im = lo; }", "if (order == 0) { *re = lo; *im = hi; }"),
     # checkerboard dropped
-    "checkerboard": ("double sgn = ((x + y) & 1) ? -1.0 : 1.0;", "double sgn = 1.0;"),
+    "checkerboard": ("double sgn = ((x + y) & 1) ? -1.0 : 1.0;\n                double wr = w[",
+                     "double sgn = 1.0;\n                double wr = w["),
+    # autocorrelation image: checkerboard dropped from the lone kernel transform
+    "auto_checkerboard": ("double sgn = ((x + y) & 1) ? -1.0 : 1.0;\n                                double wr = sgn",
+                          "double sgn = 1.0;\n                                double wr = sgn"),
+    # autocorrelation image: conjugate on the wrong factor of the correlation X Y*
+    "auto_conj": ("vxyi += xi * yr - xr * yi;", "vxyi += xr * yi - xi * yr;"),
+    # autocorrelation image: kernel cross term without the conjugate
+    "auto_kernel_conj": ("double kr = ar * br + ai * bi, ki = ai * br - ar * bi;",
+                         "double kr = ar * br - ai * bi, ki = ai * br + ar * bi;"),
     # Gaussian not normalised
     "no_norm": ("for (int k = 0; k < K * K; ++k) w[2 * k] /= sum;", "(void)sum;"),
     # rounding to nearest cell replaced by truncation
@@ -295,6 +341,7 @@ def _pins_pass() -> bool:
         for ax in (0, 1):
             test_worked_example_closed_form(ax)
         test_fx_identity_dual_pol_user_taps()
+        test_autocorr_removed_is_fx_without_diagonal()
         test_polarisation_conjugation_order()
         test_dft_orientation()
     except (AssertionError, oracle.OracleError):
