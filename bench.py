@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP16 matrix-core leg")
     ap.add_argument("--precision", choices=["fp32", "fp16", "fp8"], default=None,
                     help="override the workload's own precision")
-    ap.add_argument("--no-graph", action="store_true", help="batched workloads: eager launches, no autotuning")
+    ap.add_argument("--no-graph", action="store_true", help="batched workloads: eager launches instead of graph replay")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE hardware counters")
@@ -168,7 +168,9 @@ def main():
     # each workload's own precision; the uneven batch of sub-arrays runs as
     # one autotuned persistent launch replayed from a hipGraph
     precision = args.precision or wl.precision
-    flags = (E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH) if len(subs) > 1 and not args.no_graph else 0
+    flags = 0
+    if len(subs) > 1:
+        flags = E.EPIC_F_AUTOTUNE | (0 if args.no_graph else E.EPIC_F_GRAPH)
     ms_per_step, kern_ms, img32, info32 = run(precision, args.steps, args.warmup, flags)
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
     res = {
