@@ -72,7 +72,9 @@ enum {
     EPIC_F_GRAPH = 1u,            /* replay accumulate steps from a captured hipGraph */
     EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time */
     EPIC_F_DRY_RUN = 4u,          /* validate and size on the CPU; touch no device */
-    EPIC_F_REMOVE_AUTOCORR = 8u   /* subtract each antenna's own power term (a = b) */
+    EPIC_F_REMOVE_AUTOCORR = 8u,  /* subtract each antenna's own power term (a = b) at read-out */
+    EPIC_F_COMPLEX_WEIGHTS = 16u  /* gather with complex weights even if every tap is real, so that
+                                     epic_set_gains may pass complex (phase) gains later */
 };
 
 /*

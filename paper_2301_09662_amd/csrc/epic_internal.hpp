@@ -60,9 +60,12 @@ struct SubDev {
     int32_t* cells;           // [C][A][2] nearest cell
     double* gfrac;            // [C][A][2] fractional cell coordinate
     float* taps;              // [C][A][P][K][K][2] FP32 taps (before gains)
-    float* gains;             // [C][A][P][2] complex gains (or nullptr = unit)
+    float* gains;             // [C][A][P][2] complex gains in effect (or nullptr = unit)
+    float* gains_buf = nullptr;   // device storage of the gains once any were set
     float2* twiddle;          // [N] exp(+2 pi i r / N)
     float* slots;             // [S][C][NPP][N][N] partial accumulators
+    float* vaa = nullptr;     // [C][A][4 or 1] zero-lag antenna correlations (autocorrelation removal)
+    float* lag = nullptr;     // [C][(2K-1)^2][3 or 1][2] lag sums of the autocorrelation image
     // launch shape
     int threads;
     size_t lds_bytes;
@@ -120,6 +123,11 @@ hipError_t launch_batch(const BatchDev& bd, const uint8_t* const* samples, int n
                         hipStream_t st);
 
 // Ordered reduction of the slots into [C][NPP][N][N] (or Stokes), optional reset.
+hipError_t launch_autocorr(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
+hipError_t launch_autocorr_fold(const SubDev& d, hipStream_t st);
+hipError_t launch_zero(float* x, int64_t n, hipStream_t st);
+int64_t vaa_count(const SubDev& d);
+int64_t lag_count(const SubDev& d);
 hipError_t launch_readout(const SubDev& d, float* out, int stokes, int reset, hipStream_t st);
 
 // Debug decode of n bytes into float (re, im) pairs.

@@ -85,11 +85,131 @@ __global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const u
     }
 }
 
+// ---- autocorrelations (the a = b terms of Eq. 3) ---------------------------
+// Zero-lag correlations of every antenna over the spectra of a call:
+// vaa[c][a] += (XX*, YY*, Re XY*, Im XY*) (single pol: XX* only).  One thread
+// per (channel, antenna) sums kAutoChunk spectra in registers and adds them
+// with one atomic per product.  All values are integers below 2^24 (products
+// of 4-bit numbers, at most 128 per spectrum), so the FP32 sums are exact and
+// do not depend on the order of the atomics while a sum stays below 2^24
+// (131072 spectra at full scale between read-outs).
+constexpr int kAutoChunk = 64;
+
+__global__ void autocorr_accumulate_kernel(const uint8_t* __restrict__ samples, int64_t T, int C, int A, int P,
+                                           int nibble_order, float* __restrict__ vaa) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // c * A + a
+    if (idx >= (int64_t)C * A) return;
+    const int64_t c = idx / A, a = idx - c * A;
+    const int64_t t0 = (int64_t)blockIdx.y * kAutoChunk;
+    const int64_t t1 = (t0 + kAutoChunk < T) ? t0 + kAutoChunk : T;
+    const int64_t AP = (int64_t)A * P;
+    float xx = 0.f, yy = 0.f, xyr = 0.f, xyi = 0.f;
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint8_t* row = samples + (t * C + c) * AP + a * P;
+        const float2 x = unpack44(row[0], nibble_order);
+        xx = fmaf(x.x, x.x, fmaf(x.y, x.y, xx));
+        if (P == 2) {
+            const float2 y = unpack44(row[1], nibble_order);
+            yy = fmaf(y.x, y.x, fmaf(y.y, y.y, yy));
+            xyr = fmaf(x.x, y.x, fmaf(x.y, y.y, xyr));
+            xyi = fmaf(x.y, y.x, fmaf(-x.x, y.y, xyi));
+        }
+    }
+    const int npa = (P == 2) ? 4 : 1;
+    float* dst = vaa + idx * npa;
+    atomicAdd(dst, xx);
+    if (P == 2) {
+        atomicAdd(dst + 1, yy);
+        atomicAdd(dst + 2, xyr);
+        atomicAdd(dst + 3, xyi);
+    }
+}
+
+// Lag sums of one channel: R^{pq}(d) = sum_a V^{pq}_aa sum_u w^p_a(u + d) conj(w^q_a(u))
+// for every tap offset d in [-(K-1), K-1]^2 (the correlation of the antenna's
+// kernel with itself, weighted by its zero-lag correlation).  An antenna's
+// kernel image times its conjugate depends on these lags only, not on where
+// the antenna sits, so sum_d R(d) exp(+2 pi i d.k / N) is the image of the
+// a = b terms.  Products: 0 XX* (w^X, w^X), 1 YY* (w^Y, w^Y), 2 XY* (w^X, w^Y).
+// Block (lag, channel); threads stride over antennas; FP64 sums, added into
+// the lag accumulator (which thus holds the a = b terms of several stretches
+// of an integration with different gains).
+// lag layout: [C][L][npl][2] with L = (2K-1)^2, npl = 3 (dual pol) or 1.
+__global__ void autocorr_lag_kernel(const float* __restrict__ vaa, const float* __restrict__ taps,
+                                    const float* __restrict__ gains, float* __restrict__ lag, int C, int A, int P,
+                                    int K) {
+    const int L1 = 2 * K - 1;
+    const int l = blockIdx.x, c = blockIdx.y;
+    const int ddy = l / L1 - (K - 1), ddx = l % L1 - (K - 1);
+    const int npl = (P == 2) ? 3 : 1, npa = (P == 2) ? 4 : 1;
+    double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int a = threadIdx.x; a < A; a += blockDim.x) {
+        const float* v = vaa + ((int64_t)c * A + a) * npa;
+        for (int q = 0; q < npl; ++q) {
+            const int pa = (q == 1) ? 1 : 0, pb = (q == 0) ? 0 : 1;
+            double gr[2] = {1.0, 1.0}, gi[2] = {0.0, 0.0};
+            if (gains)
+                for (int h = 0; h < 2; ++h) {
+                    const int p = h ? pb : pa;
+                    const int64_t gix = (((int64_t)c * A + a) * P + p) * 2;
+                    gr[h] = gains[gix];
+                    gi[h] = gains[gix + 1];
+                }
+            double sr = 0.0, si = 0.0;   // sum_u w^pa(u + d) conj(w^pb(u))
+            for (int uy = 0; uy < K; ++uy) {
+                const int vy = uy + ddy;
+                if (vy < 0 || vy >= K) continue;
+                for (int ux = 0; ux < K; ++ux) {
+                    const int vx = ux + ddx;
+                    if (vx < 0 || vx >= K) continue;
+                    const float* ta = taps + ((((int64_t)c * A + a) * P + pa) * K * K + vy * K + vx) * 2;
+                    const float* tb = taps + ((((int64_t)c * A + a) * P + pb) * K * K + uy * K + ux) * 2;
+                    // gains applied to the taps as the gridding does
+                    const double ar = gr[0] * ta[0] - gi[0] * ta[1], ai = gr[0] * ta[1] + gi[0] * ta[0];
+                    const double br = gr[1] * tb[0] - gi[1] * tb[1], bi = gr[1] * tb[1] + gi[1] * tb[0];
+                    sr += ar * br + ai * bi;
+                    si += ai * br - ar * bi;
+                }
+            }
+            double vr, vi;
+            if (q == 0) { vr = v[0]; vi = 0.0; }
+            else if (q == 1) { vr = v[1]; vi = 0.0; }
+            else { vr = v[2]; vi = v[3]; }
+            acc[q][0] += vr * sr - vi * si;
+            acc[q][1] += vr * si + vi * sr;
+        }
+    }
+    // block reduction (fixed order: deterministic)
+    __shared__ double red[256][6];
+    for (int q = 0; q < 3; ++q) {
+        red[threadIdx.x][2 * q] = acc[q][0];
+        red[threadIdx.x][2 * q + 1] = acc[q][1];
+    }
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 6; ++k) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int L = L1 * L1;
+        float* out = lag + (((int64_t)c * L + l) * npl) * 2;
+        for (int q = 0; q < npl; ++q) {
+            out[2 * q] += (float)red[0][2 * q];
+            out[2 * q + 1] += (float)red[0][2 * q + 1];
+        }
+    }
+}
+
 // out[c][k][j][i] = sum_s slots[s][c][k][j][i], summed in slot order so the
-// result is identical from run to run; Stokes form on request (linear feeds:
-// I = XX+YY, Q = XX-YY, U = 2 Re XY*, V = -2 Im XY*); optional reset.
+// result is identical from run to run; minus the autocorrelation image when
+// lag != nullptr; Stokes form on request (linear feeds: I = XX+YY, Q = XX-YY,
+// U = 2 Re XY*, V = -2 Im XY*); optional reset of the slots.
+// The autocorrelation image at pixel (i, j) reads frequency bin k = (i + N/2,
+// j + N/2) mod N, where exp(+2 pi i d.k / N) = (-1)^(dx+dy) exp(+2 pi i (dx i + dy j) / N).
 __global__ void readout_kernel(float* __restrict__ slots, float* __restrict__ out, int S, int C, int NPP,
-                               int NN, int stokes, int reset) {
+                               int N, int stokes, int reset, const float* __restrict__ lag, int K) {
+    const int NN = N * N;
     const int64_t per_slot = (int64_t)C * NPP * NN;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over C * NN pixels
     if (idx >= (int64_t)C * NN) return;
@@ -97,6 +217,32 @@ __global__ void readout_kernel(float* __restrict__ slots, float* __restrict__ ou
     float v[4] = {0.f, 0.f, 0.f, 0.f};
     for (int s = 0; s < S; ++s)
         for (int k = 0; k < NPP; ++k) v[k] += slots[s * per_slot + (c * NPP + k) * NN + pix];
+    if (lag) {
+        const int i = (int)(pix % N), j = (int)(pix / N);
+        const int L1 = 2 * K - 1, npl = (NPP == 4) ? 3 : 1;
+        const float* lc = lag + (int64_t)c * L1 * L1 * npl * 2;
+        float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
+        for (int l = 0; l < L1 * L1; ++l) {
+            const int dy = l / L1 - (K - 1), dx = l % L1 - (K - 1);
+            int r = (dx * i + dy * j) % N;
+            if (r < 0) r += N;
+            double sn, cs;
+            sincospi(2.0 * (double)r / (double)N, &sn, &cs);
+            const float sg = ((dx + dy) & 1) ? -1.f : 1.f;
+            const float er = sg * (float)cs, ei = sg * (float)sn;
+            for (int q = 0; q < npl; ++q) {
+                const float lr = lc[(l * npl + q) * 2], li = lc[(l * npl + q) * 2 + 1];
+                ar[q] = fmaf(lr, er, fmaf(-li, ei, ar[q]));
+                ai[q] = fmaf(lr, ei, fmaf(li, er, ai[q]));
+            }
+        }
+        v[0] -= ar[0];
+        if (NPP == 4) {
+            v[1] -= ar[1];
+            v[2] -= ar[2];
+            v[3] -= ai[2];
+        }
+    }
     if (stokes && NPP == 4) {
         const float I = v[0] + v[1], Q = v[0] - v[1], U = 2.0f * v[2], V = -2.0f * v[3];
         v[0] = I; v[1] = Q; v[2] = U; v[3] = V;
@@ -105,6 +251,11 @@ __global__ void readout_kernel(float* __restrict__ slots, float* __restrict__ ou
     if (reset)
         for (int s = 0; s < S; ++s)
             for (int k = 0; k < NPP; ++k) slots[s * per_slot + (c * NPP + k) * NN + pix] = 0.0f;
+}
+
+__global__ void zero_kernel(float* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0f;
 }
 
 __global__ void unpack_debug_kernel(const uint8_t* __restrict__ in, int64_t n, int order, float2* __restrict__ out) {
@@ -135,12 +286,46 @@ hipError_t launch_entry_weights(const SubDev& d, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_autocorr(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
+    const int64_t n = (int64_t)d.C * d.A;
+    const int bs = 256;
+    const int64_t chunks = (n_time + kAutoChunk - 1) / kAutoChunk;
+    if (chunks > 65535) return hipErrorInvalidValue;
+    autocorr_accumulate_kernel<<<dim3((unsigned)((n + bs - 1) / bs), (unsigned)chunks), dim3(bs), 0, st>>>(
+        samples, n_time, d.C, d.A, d.P, d.nibble_order, d.vaa);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(float* x, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    zero_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(x, n);
+    return hipGetLastError();
+}
+
+int64_t vaa_count(const SubDev& d) { return (int64_t)d.C * d.A * (d.P == 2 ? 4 : 1); }
+int64_t lag_count(const SubDev& d) { return (int64_t)d.C * (2 * d.K - 1) * (2 * d.K - 1) * (d.P == 2 ? 3 : 1) * 2; }
+
+// Move the zero-lag correlations gathered so far into the lag accumulator
+// (with the gains in effect while they were gathered) and clear them.
+hipError_t launch_autocorr_fold(const SubDev& d, hipStream_t st) {
+    if (!d.vaa) return hipSuccess;
+    const int L1 = 2 * d.K - 1;
+    autocorr_lag_kernel<<<dim3(L1 * L1, d.C), dim3(256), 0, st>>>(d.vaa, d.taps, d.gains, d.lag, d.C, d.A, d.P, d.K);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_zero(d.vaa, vaa_count(d), st);
+}
+
 hipError_t launch_readout(const SubDev& d, float* out, int stokes, int reset, hipStream_t st) {
     const int64_t n = (int64_t)d.C * d.N * d.N;
     const int bs = 256;
-    readout_kernel<<<dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st>>>(d.slots, out, d.S, d.C, d.NPP, d.N * d.N,
-                                                                            stokes, reset);
-    return hipGetLastError();
+    hipError_t e = launch_autocorr_fold(d, st);
+    if (e != hipSuccess) return e;
+    readout_kernel<<<dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st>>>(
+        d.slots, out, d.S, d.C, d.NPP, d.N, stokes, reset, d.vaa ? d.lag : nullptr, d.K);
+    e = hipGetLastError();
+    if (e != hipSuccess || !reset || !d.vaa) return e;
+    return launch_zero(d.lag, lag_count(d), st);
 }
 
 hipError_t launch_unpack_debug(const uint8_t* in, int64_t n, int order, float* out, hipStream_t st) {

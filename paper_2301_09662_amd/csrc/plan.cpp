@@ -24,7 +24,8 @@ namespace {
 
 constexpr double kC0 = 299792458.0;   // m/s
 constexpr uint32_t kMagic = 0x45504943u;  // 'EPIC'
-constexpr uint32_t kKnownFlags = EPIC_F_GRAPH | EPIC_F_AUTOTUNE | EPIC_F_DRY_RUN | EPIC_F_REMOVE_AUTOCORR;
+constexpr uint32_t kKnownFlags =
+    EPIC_F_GRAPH | EPIC_F_AUTOTUNE | EPIC_F_DRY_RUN | EPIC_F_REMOVE_AUTOCORR | EPIC_F_COMPLEX_WEIGHTS;
 
 struct SubHost {
     epic_array_desc desc{};
@@ -63,6 +64,11 @@ struct epic_plan_s {
     hipGraphExec_t exec = nullptr;
     int64_t graph_T = -1;
     std::vector<const uint8_t*> graph_ptrs;
+    // host staging of epic_set_gains (pinned, reused once its copy is done)
+    float* gain_stage = nullptr;
+    size_t gain_stage_n = 0;
+    hipEvent_t gain_ev = nullptr;
+    int gain_ev_pending = 0;
 };
 
 namespace {
@@ -212,6 +218,9 @@ void free_all(epic_plan_s* p) {
     if (!p->dry_run) {
         hipSetDevice(p->device);
         hipDeviceSynchronize();
+        if (p->gain_ev) hipEventDestroy(p->gain_ev);
+        if (p->gain_stage) hipHostFree(p->gain_stage);
+        p->gain_ev = nullptr; p->gain_stage = nullptr;
         if (p->exec) hipGraphExecDestroy(p->exec);
         if (p->graph) hipGraphDestroy(p->graph);
         if (p->cap_stream) hipStreamDestroy(p->cap_stream);
@@ -320,12 +329,24 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st) {
 
 // The kernel launches of one accumulate step.
 hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
-    if (p->batched) return launch_batch(p->bd, d_samples, (int)p->subs.size(), n_time, st);
+    if (p->batched) {
+        hipError_t e = launch_batch(p->bd, d_samples, (int)p->subs.size(), n_time, st);
+        if (e != hipSuccess) return e;
+    } else {
+        for (size_t k = 0; k < p->subs.size(); ++k) {
+            const SubDev& d = p->subs[k].dev;
+            hipError_t e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
+                                                      : launch_mfma(d, d_samples[k], n_time, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    // zero-lag antenna correlations for the autocorrelation removal at read-out
     for (size_t k = 0; k < p->subs.size(); ++k) {
         const SubDev& d = p->subs[k].dev;
-        hipError_t e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
-                                                  : launch_mfma(d, d_samples[k], n_time, st);
-        if (e != hipSuccess) return e;
+        if (d.vaa) {
+            hipError_t e = launch_autocorr(d, d_samples[k], n_time, st);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -373,7 +394,7 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         SubDev& d = h.dev;
         d.A = h.desc.n_ant; d.P = h.desc.n_pol; d.C = h.desc.n_chan; d.N = h.desc.grid_n;
         d.K = h.desc.kernel_k; d.NPP = (d.P == 2) ? 4 : 1; d.nibble_order = h.desc.nibble_order;
-        d.real_taps = 1;
+        d.real_taps = (desc->flags & EPIC_F_COMPLEX_WEIGHTS) ? 0 : 1;
         for (size_t k = 1; k < h.user_taps.size(); k += 2)
             if (h.user_taps[k] != 0.0f) { d.real_taps = 0; break; }
     }
@@ -450,6 +471,14 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if ((s = hip_status(launch_dft_matrix(d, st))) != EPIC_OK) return s;
         }
         if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
+        if (desc->flags & EPIC_F_REMOVE_AUTOCORR) {
+            const size_t nv = (size_t)d.C * d.A * (d.P == 2 ? 4 : 1);
+            const size_t nl = (size_t)d.C * (2 * d.K - 1) * (2 * d.K - 1) * (d.P == 2 ? 3 : 1) * 2;
+            if ((s = dalloc(p, &d.vaa, nv)) != EPIC_OK) return s;
+            if ((s = dalloc(p, &d.lag, nl)) != EPIC_OK) return s;
+            if ((s = hip_status(hipMemsetAsync(d.vaa, 0, nv * sizeof(float), st))) != EPIC_OK) return s;
+            if ((s = hip_status(hipMemsetAsync(d.lag, 0, nl * sizeof(float), st))) != EPIC_OK) return s;
+        }
     }
     if (p->batched) {
         p->table.clear();
@@ -510,6 +539,8 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
     if (desc->output != EPIC_OUT_POL && desc->output != EPIC_OUT_STOKES) return EPIC_E_ARG;
     if (desc->max_time < 1 || desc->device < 0) return EPIC_E_ARG;
     if (desc->flags & ~kKnownFlags) return EPIC_E_ARG;
+    // the zero-lag correlation pass covers 64 spectra per grid row, 65535 rows
+    if ((desc->flags & EPIC_F_REMOVE_AUTOCORR) && desc->max_time > 65535LL * 64) return EPIC_E_UNSUPPORTED;
     for (int k = 0; k < 4; ++k)
         if (desc->reserved[k] != 0) return EPIC_E_ARG;
     for (int k = 0; k < desc->n_sub; ++k) {
@@ -519,7 +550,6 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
     }
     if (desc->precision == EPIC_FP8) return EPIC_E_UNSUPPORTED;
     if (desc->gridder != EPIC_GRID_AUTO && desc->gridder != EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
-    if (desc->flags & EPIC_F_REMOVE_AUTOCORR) return EPIC_E_UNSUPPORTED;
     epic_plan_s* p = new (std::nothrow) epic_plan_s();
     if (!p) return EPIC_E_NOMEM;
     epic_status s;
@@ -571,10 +601,52 @@ epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, v
 }
 
 epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, void* hip_stream) {
-    (void)h_gains; (void)hip_stream;
     if (!valid_plan(p) || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
     if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;
-    return EPIC_E_UNSUPPORTED;
+    SubDev& d = p->subs[sub].dev;
+    const size_t n = (size_t)d.C * d.A * d.P * 2;
+    if (h_gains) {
+        for (size_t k = 0; k < n; ++k)
+            if (!std::isfinite(h_gains[k])) return EPIC_E_ARG;
+        if (d.real_taps)
+            for (size_t k = 1; k < n; k += 2)
+                if (h_gains[k] != 0.0f) return EPIC_E_UNSUPPORTED;   // needs EPIC_F_COMPLEX_WEIGHTS
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
+    // the autocorrelations gathered so far belong to the old gains
+    hipError_t e = launch_autocorr_fold(d, st);
+    if (e != hipSuccess) return check_device(p, e);
+    if (!h_gains) {
+        d.gains = nullptr;
+    } else {
+        if (!d.gains_buf) {
+            epic_status s = dalloc(p, &d.gains_buf, n);
+            if (s != EPIC_OK) return s;
+        }
+        if (!p->gain_ev && hipEventCreateWithFlags(&p->gain_ev, hipEventDisableTiming) != hipSuccess)
+            return check_device(p, hipErrorUnknown);
+        if (p->gain_ev_pending) {   // the staging buffer is free once its last copy is done
+            if (hipEventSynchronize(p->gain_ev) != hipSuccess) return check_device(p, hipErrorUnknown);
+            p->gain_ev_pending = 0;
+        }
+        if (p->gain_stage_n < n) {
+            if (p->gain_stage) hipHostFree(p->gain_stage);
+            p->gain_stage = nullptr;
+            p->gain_stage_n = 0;
+            if (hipHostMalloc(reinterpret_cast<void**>(&p->gain_stage), n * sizeof(float), hipHostMallocDefault) !=
+                hipSuccess)
+                return EPIC_E_NOMEM;
+            p->gain_stage_n = n;
+        }
+        std::memcpy(p->gain_stage, h_gains, n * sizeof(float));
+        e = hipMemcpyAsync(d.gains_buf, p->gain_stage, n * sizeof(float), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(p->gain_ev, st);
+        if (e != hipSuccess) return check_device(p, e);
+        p->gain_ev_pending = 1;
+        d.gains = d.gains_buf;
+    }
+    return check_device(p, launch_entry_weights(d, st));
 }
 
 epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {

@@ -30,7 +30,7 @@ EPIC_OK, EPIC_E_ARG, EPIC_E_GEOMETRY, EPIC_E_NOMEM, EPIC_E_DEVICE, EPIC_E_UNSUPP
 EPIC_FP32, EPIC_FP16, EPIC_FP8 = 0, 1, 2
 EPIC_GRID_AUTO, EPIC_GRID_GATHER, EPIC_GRID_DENSE_GEMM, EPIC_GRID_BLOCK_GEMM = 0, 1, 2, 3
 EPIC_OUT_POL, EPIC_OUT_STOKES = 0, 1
-EPIC_F_GRAPH, EPIC_F_AUTOTUNE, EPIC_F_DRY_RUN, EPIC_F_REMOVE_AUTOCORR = 1, 2, 4, 8
+EPIC_F_GRAPH, EPIC_F_AUTOTUNE, EPIC_F_DRY_RUN, EPIC_F_REMOVE_AUTOCORR, EPIC_F_COMPLEX_WEIGHTS = 1, 2, 4, 8, 16
 PRECISIONS = {"fp32": EPIC_FP32, "fp16": EPIC_FP16, "fp8": EPIC_FP8}
 
 

@@ -1,0 +1,200 @@
+"""GPU parity of the steps adjacent to the hot path: autocorrelation removal
+(every antenna's own a = b term subtracted at read-out), per-antenna complex
+gains folded into the taps (changed between calls), and the Stokes output.
+
+Tolerances as for the plain path (1e-5 FP32, 1e-3 FP16 per image), with the
+errors of an autocorrelation-removed image measured against the norm and
+peak of the full image: the GPU forms the full sum and the a = b image in
+FP32 and subtracts, so its rounding scales with the full image, not with the
+(smaller) difference.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_parity, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2301_09662_amd import epic
+    return epic
+
+
+def removed_errors(gpu, ref, full):
+    """Per-image errors of an autocorrelation-removed cube, normalised by the
+    full image (cross products by sqrt(|XX| |YY|) of the full image)."""
+    C, npp = ref.shape[:2]
+    fro = np.zeros((C, npp))
+    mx = np.zeros((C, npp))
+    for c in range(C):
+        nx = np.linalg.norm(full[c, 0])
+        ny = np.linalg.norm(full[c, 1]) if npp == 4 else nx
+        peak = np.abs(full[c, : min(npp, 2)]).max()
+        for k in range(npp):
+            den = np.linalg.norm(full[c, k]) if k < 2 else np.sqrt(nx * ny)
+            fro[c, k] = np.linalg.norm(gpu[c, k] - ref[c, k]) / den
+            mx[c, k] = np.abs(gpu[c, k] - ref[c, k]).max() / peak
+    return fro.max(), mx.max()
+
+
+def run_plan(E, subs, steps, precision="fp32", flags=0, output=0, taps=None, max_time=None):
+    """steps: list of ("acc", [samples per sub]) / ("gains", sub, array or None) /
+    ("read", reset); returns the list of read-out cubes (float64)."""
+    torch, dev = torch_dev()
+    mt = max_time or max(s[1][0].shape[0] for s in steps if s[0] == "acc")
+    plan = E.epic_plan(subs, precision=precision, max_time=mt, flags=flags, output=output, taps=taps)
+    outs = []
+    try:
+        info = E.epic_plan_query(plan)
+        for st in steps:
+            if st[0] == "acc":
+                d = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in st[1]]
+                E.epic_grid_fft_accumulate(plan, d, st[1][0].shape[0])
+                torch.cuda.synchronize()
+            elif st[0] == "gains":
+                E.epic_set_gains(plan, st[1], st[2])
+            else:
+                o = [torch.full((s.n_chan, info["npp"][k], s.grid_n, s.grid_n), float("nan"), device=dev)
+                     for k, s in enumerate(subs)]
+                E.epic_readout(plan, o, st[1])
+                torch.cuda.synchronize()
+                outs.append([t.double().cpu().numpy() for t in o])
+    finally:
+        E.epic_destroy(plan)
+    return outs
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp16", 1e-3)])
+def test_autocorr_removed_station_subset(E, precision, tol):
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=3)
+    x = synth.samples(sub, 24)
+    (out,) = run_plan(E, [sub], [("acc", [x]), ("read", 1)], precision, flags=E.EPIC_F_REMOVE_AUTOCORR)
+    full = oracle.image(sub, x)
+    ref = full - oracle.autocorr(sub, x)
+    fro, mx = removed_errors(out[0], ref, full)
+    print(f"{precision} autocorr removed: rel err {fro:.2e}, max |d|/peak {mx:.2e}; "
+          f"removed / full image norm {np.linalg.norm(ref[:, 0]) / np.linalg.norm(full[:, 0]):.3f}")
+    assert fro <= tol and mx <= tol
+
+
+def test_autocorr_removed_single_pol_and_integrations(E):
+    """Single pol, two integrations: the second read-out holds only its own
+    spectra (accumulators and autocorrelations reset), split over two calls."""
+    sub = synth.workload(1).subs[0]
+    x = synth.samples(sub, 64)
+    outs = run_plan(E, [sub], [("acc", [x[:40]]), ("read", 1), ("acc", [x[40:50]]), ("acc", [x[50:]]),
+                               ("read", 1)], flags=E.EPIC_F_REMOVE_AUTOCORR, max_time=40)
+    for o, xs in zip(outs, (x[:40], x[40:])):
+        full = oracle.image(sub, xs)
+        fro, mx = removed_errors(o[0], full - oracle.autocorr(sub, xs), full)
+        assert fro <= 1e-5 and mx <= 1e-5
+
+
+def test_autocorr_removed_batched_graph(E):
+    subs = [synth.shrink(s, n_chan=n) for s, n in zip(synth.workload(4).subs, (2, 2, 1))]
+    xs = [synth.samples(s, 12) for s in subs]
+    flags = E.EPIC_F_REMOVE_AUTOCORR | E.EPIC_F_GRAPH | E.EPIC_F_AUTOTUNE
+    (out,) = run_plan(E, subs, [("acc", [x[:6] for x in xs]), ("acc", [x[6:] for x in xs]), ("read", 1)],
+                      "fp16", flags=flags)
+    for k, (s, x) in enumerate(zip(subs, xs)):
+        full = oracle.image(s, x)
+        fro, mx = removed_errors(out[k], full - oracle.autocorr(s, x), full)
+        assert fro <= 1e-3 and mx <= 1e-3, f"sub {k}: {fro:.2e} {mx:.2e}"
+
+
+def test_autocorr_removed_user_complex_taps(E):
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=64)
+    x = synth.samples(sub, 16)
+    taps = np.random.default_rng(11).standard_normal((2, 64, 2, 3, 3, 2)).astype(np.float32)
+    (out,) = run_plan(E, [sub], [("acc", [x]), ("read", 1)], flags=E.EPIC_F_REMOVE_AUTOCORR, taps=[taps])
+    full = oracle.image(sub, x, taps=taps)
+    fro, mx = removed_errors(out[0], full - oracle.autocorr(sub, x, taps=taps), full)
+    assert fro <= 1e-5 and mx <= 1e-5
+
+
+def user_taps(z):
+    """complex [C][A][P][K][K] -> float32 [C][A][P][K][K][2] (the taps argument)."""
+    return np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1).astype(np.float32))
+
+
+def gained_taps(sub, taps, gains):
+    """Taps (float32 [...][2]) times per-antenna gains, product in FP64: what
+    the library folds into its gather weights before rounding to FP32."""
+    t = taps[..., 0].astype(np.float64) + 1j * taps[..., 1]
+    g = gains[..., 0].astype(np.float64) + 1j * gains[..., 1]
+    return user_taps(t * g[:, :, :, None, None])
+
+
+def test_gains_between_calls_with_autocorr_removal(E):
+    """Complex gains g1 for the first call, g2 for the second, within one
+    integration: the image is the sum of the two calls' images with their own
+    gains, and the removed a = b terms follow the gains of each call."""
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=96)
+    x = synth.samples(sub, 20)
+    rng = np.random.default_rng(12)
+    taps = user_taps(oracle.taps(sub))                              # the default Gaussian, as user taps
+    g1 = rng.standard_normal((2, 96, 2, 2)).astype(np.float32)
+    g2 = rng.standard_normal((2, 96, 2, 2)).astype(np.float32)
+    flags = E.EPIC_F_REMOVE_AUTOCORR | E.EPIC_F_COMPLEX_WEIGHTS
+    steps = [("gains", 0, g1), ("acc", [x[:8]]), ("gains", 0, g2), ("acc", [x[8:]]), ("read", 1)]
+    (out,) = run_plan(E, [sub], steps, flags=flags, taps=[taps])
+    t1, t2 = gained_taps(sub, taps, g1), gained_taps(sub, taps, g2)
+    full = oracle.image(sub, x[:8], taps=t1) + oracle.image(sub, x[8:], taps=t2)
+    ref = full - oracle.autocorr(sub, x[:8], taps=t1) - oracle.autocorr(sub, x[8:], taps=t2)
+    fro, mx = removed_errors(out[0], ref, full)
+    assert fro <= 1e-5 and mx <= 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp16", 1e-3)])
+def test_gains_complex_and_reset_to_unit(E, precision, tol):
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=128)
+    x = synth.samples(sub, 10)
+    g = np.random.default_rng(13).standard_normal((2, 128, 2, 2)).astype(np.float32)
+    steps = [("gains", 0, g), ("acc", [x]), ("read", 1), ("gains", 0, None), ("acc", [x]), ("read", 1)]
+    o1, o2 = run_plan(E, [sub], steps, precision, flags=E.EPIC_F_COMPLEX_WEIGHTS)
+    taps = user_taps(oracle.taps(sub))
+    assert_parity(o1[0], oracle.image(sub, x, taps=gained_taps(sub, taps, g)), tol, "gains")
+    assert_parity(o2[0], oracle.image(sub, x), tol, "unit gains again")
+
+
+def test_real_gains_on_real_plan_and_complex_refused(E):
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=1, n_ant=64)
+    x = synth.samples(sub, 6)
+    g = np.zeros((1, 64, 2, 2), dtype=np.float32)
+    g[..., 0] = np.random.default_rng(14).uniform(0.5, 2.0, (1, 64, 2))
+    (o,) = run_plan(E, [sub], [("gains", 0, g), ("acc", [x]), ("read", 1)])
+    taps = user_taps(oracle.taps(sub))
+    assert_parity(o[0], oracle.image(sub, x, taps=gained_taps(sub, taps, g)), 1e-5, "real gains")
+    torch, dev = torch_dev()
+    plan = E.epic_plan([sub], max_time=6)
+    try:
+        gc = g.copy()
+        gc[0, 0, 0, 1] = 0.5
+        with pytest.raises(E.EpicError) as ei:
+            E.epic_set_gains(plan, 0, gc)
+        assert ei.value.status == E.EPIC_E_UNSUPPORTED
+        gn = g.copy()
+        gn[0, 1, 1, 0] = np.nan
+        with pytest.raises(E.EpicError):
+            E.epic_set_gains(plan, 0, gn)
+    finally:
+        E.epic_destroy(plan)
+
+
+@pytest.mark.parametrize("flags", [0, 8])
+def test_stokes_output(E, flags):
+    """I = XX+YY, Q = XX-YY, U = 2 Re XY*, V = -2 Im XY* (linear feeds), also
+    after autocorrelation removal."""
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    x = synth.samples(sub, 12)
+    (o,) = run_plan(E, [sub], [("acc", [x]), ("read", 1)], flags=flags, output=E.EPIC_OUT_STOKES)
+    full = oracle.image(sub, x)
+    pol = full - (oracle.autocorr(sub, x) if flags else 0.0)
+    st = np.stack([pol[:, 0] + pol[:, 1], pol[:, 0] - pol[:, 1], 2 * pol[:, 2], -2 * pol[:, 3]], axis=1)
+    fst = np.stack([full[:, 0] + full[:, 1], full[:, 0] - full[:, 1], 2 * full[:, 2], -2 * full[:, 3]], axis=1)
+    peak = np.abs(fst[:, 0]).max()
+    assert np.abs(o[0] - st).max() <= 1e-5 * peak
