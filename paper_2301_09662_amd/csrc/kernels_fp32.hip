@@ -70,26 +70,41 @@ struct Shape {
 constexpr int kPrefetch = 1;   // sample words per thread held in registers ahead of use (more are loaded directly)
 
 // ---- DFT input fold ---------------------------------------------------------
-// z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * stride] * w_Q^{n2 q}.
-// The window is zero-padded to whole blocks of 8, so every block is full and
-// the only control flow is the uniform block count nb.  s_tw is the LDS table
-// exp(+2 pi i r / N); tw holds w_N^{n1 q}.
+// z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * stride] * w_Q^{n2 q} over
+// the len non-zero inputs, nb = ceil(len / 8).  The window is zero-padded to
+// whole blocks of 8, so the first block is a plain load and no block needs a
+// bounds check; when the last block's non-zero part fits in its first half,
+// only that half is folded.  Control flow depends only on len (uniform).
+// s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}.
 template <int N>
-__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int stride, int nb,
+__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int stride, int len,
                                              const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = v[k * stride];
+    const int nb = (len + 7) >> 3;
     int widx = 0;   // (8 n2 q) mod N
     // not unrolled: an unrolled loop lets the compiler hoist every block's LDS
     // loads above the exit test, which costs ~100 registers
 #pragma unroll 1
-    for (int n2 = 1; n2 < nb; ++n2) {
+    for (int n2 = 1; n2 < nb - 1; ++n2) {
         widx += 8 * q;
         if (widx >= N) widx -= N;
         const float2 w = s_tw[widx];
         const float2* vb = v + 8 * n2 * stride;
 #pragma unroll
         for (int k = 0; k < 8; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+    }
+    if (nb >= 2) {
+        widx += 8 * q;
+        if (widx >= N) widx -= N;
+        const float2 w = s_tw[widx];
+        const float2* vb = v + 8 * (nb - 1) * stride;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+        if (len - 8 * (nb - 1) > 4) {
+#pragma unroll
+            for (int k = 4; k < 8; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+        }
     }
 #pragma unroll
     for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], tw[n1]);   // tw[0] = 1
@@ -191,7 +206,6 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         const int slot = slot_of(g, v, t, T, 0, 1, L);
         const ChanInfo ci = a.chans[c];
         const int R = ci.R, W = ci.W, n_cell = ci.n_cell;
-        const int nbR = (R + 7) >> 3, nbW = (W + 7) >> 3;
         const CellDesc* g_desc = a.cells_desc + ci.cell_off;
         const uint2* g_gant = a.grp_ant + ci.grp_off;
         const float4* g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
@@ -256,7 +270,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                     const int p = (P == 2 && rr >= R) ? 1 : 0;
                     const int r = rr - p * R;
                     float2 z[8];
-                    fold_twiddle<N>(z, s_G + (p * a.Rmax + r) * a.WP, 1, nbW, tw, s_tw, q);
+                    fold_twiddle<N>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, s_tw, q);
                     fft8(z);
                     float2* yrow = s_Y + (p * a.Rmax + r) * a.YP;
 #pragma unroll
@@ -279,11 +293,11 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             // 3b + 4. column pass per pol, products and accumulation in registers
             if (lane_on) {
                 float2 X[8];
-                fold_twiddle<N>(X, s_Y + kk, a.YP, nbR, tw, s_tw, q);
+                fold_twiddle<N>(X, s_Y + kk, a.YP, R, tw, s_tw, q);
                 fft8(X);
                 if constexpr (P == 2) {
                     float2 Yv[8];
-                    fold_twiddle<N>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, nbR, tw, s_tw, q);
+                    fold_twiddle<N>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, R, tw, s_tw, q);
                     fft8(Yv);
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
