@@ -188,6 +188,24 @@ epic_status epic_grid_fft_accumulate(epic_plan_t plan, const uint8_t* const* d_s
 epic_status epic_readout(epic_plan_t plan, float* const* d_images, int32_t reset, void* hip_stream);
 
 /*
+ * epic_efield -- electric-field images instead of accumulated products (the
+ * method can emit field images as well as intensity images, Sec. 1): for every
+ * spectrum t, channel c and polarisation p of sub-array `sub`, the transform
+ * FT^-1[sum_a W_a * E_a] of Eq. 4 before squaring, with the (-1)^(x+y) grid
+ * centring, i.e. the field whose squared magnitude summed over t is the XX*
+ * (or YY*) image of epic_readout.
+ *   d_samples   device uint8 [n_time][C][A][P] of this sub-array.
+ *   d_out       device float [n_time][C][P][N][N][2] (re, im), indexed
+ *               [t][c][p][j][i] with pixels as for epic_readout; overwritten.
+ *   n_time      0..max_time (0 is a no-op).
+ * Enqueued on hip_stream; the plan's accumulators are untouched.  FP32 plans
+ * only (EPIC_E_UNSUPPORTED otherwise).
+ * Errors: EPIC_E_ARG, EPIC_E_STATE, EPIC_E_UNSUPPORTED, EPIC_E_DEVICE.
+ */
+epic_status epic_efield(epic_plan_t plan, int32_t sub, const uint8_t* d_samples, int64_t n_time, float* d_out,
+                        void* hip_stream);
+
+/*
  * epic_set_gains -- per-antenna complex gains (delay / phase / amplitude
  * corrections, Sec. 2.2's delay correction step) folded into the kernel taps
  * of one sub-array: tap'(c, a, p) = g(c, a, p) * tap(c, a, p).  Replaces any

@@ -68,9 +68,10 @@ def _load():
         lib.ora_image_range.argtypes = [P(_OraArray), P(ctypes.c_uint8), ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_int, P(ctypes.c_double), ctypes.c_int]
         lib.ora_autocorr_range.argtypes = lib.ora_image_range.argtypes
+        lib.ora_efield_range.argtypes = lib.ora_image_range.argtypes
         lib.ora_max_threads.argtypes = []
         for f in ("ora_unpack_table", "ora_geometry", "ora_taps", "ora_grid", "ora_dft2",
-                  "ora_image_range", "ora_autocorr_range", "ora_max_threads"):
+                  "ora_image_range", "ora_autocorr_range", "ora_efield_range", "ora_max_threads"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -203,6 +204,27 @@ def autocorr(sub, samples: np.ndarray, chans: Optional[range] = None, n_threads:
     """FP64 [C][NPP][N][N]: the a = b terms of the image, sum over antennas of
     K^p_a K^q_a^* sum_t E^p_a E^q_a^* (K^p_a: antenna a's kernel transformed alone)."""
     return _run("ora_autocorr_range", sub, samples, chans, n_threads, **kw)
+
+
+def efield(sub, samples: np.ndarray, chans: Optional[range] = None, n_threads: int = 0, **kw) -> np.ndarray:
+    """complex128 [T][C][P][N][N]: each spectrum's transformed field per
+    polarisation (steps 1-3, before the products); channels outside ``chans``
+    are zero."""
+    s = _spec(sub, **kw)
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.uint8)
+    T = samples.shape[0]
+    if samples.shape[1:] != (s.n_chan, s.n_ant, s.n_pol):
+        raise ValueError(f"samples shape {samples.shape} does not match the array")
+    N = s.grid_n
+    out = np.zeros((T, s.n_chan, s.n_pol, N, N, 2), dtype=np.float64)
+    c0, c1 = (0, s.n_chan) if chans is None else (chans.start, chans.stop)
+    st = s.c_struct()
+    rc = lib.ora_efield_range(ctypes.byref(st), _ptr(samples, ctypes.c_uint8), int(T), int(c0), int(c1),
+                              _ptr(out, ctypes.c_double), int(n_threads))
+    if rc:
+        raise OracleError(rc, "ora_efield_range")
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def _run(fn, sub, samples, chans, n_threads, **kw):

@@ -380,6 +380,62 @@ int ora_autocorr_range(const ora_array* s, const uint8_t* samples, int64_t T,
     return nomem ? ORA_E_NOMEM : ORA_OK;
 }
 
+/* ---- steps 1-3 only: electric-field images ------------------------------ */
+/*
+ * out: FP64 [T][C][P][N][N][2] (overwritten for the channel range): for every
+ * spectrum the transformed field of step 3 of each polarisation, before the
+ * products of step 4.  Same arguments as ora_image_range otherwise.
+ */
+int ora_efield_range(const ora_array* s, const uint8_t* samples, int64_t T,
+                     int chan_begin, int chan_end, double* out, int n_threads) {
+    int rc = check_array(s);
+    if (rc) return rc;
+    if (!samples || !out || T < 0) return ORA_E_ARG;
+    if (chan_begin < 0 || chan_end > s->n_chan || chan_begin > chan_end) return ORA_E_ARG;
+    const int N = s->grid_n, A = s->n_ant, P = s->n_pol, C = s->n_chan, K = s->kernel_k;
+    const size_t NN = (size_t)N * N;
+
+    int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * (size_t)C * A * 2);
+    double* g = (double*)malloc(sizeof(double) * (size_t)C * A * 2);
+    double* taps = (double*)malloc(sizeof(double) * (size_t)C * A * P * K * K * 2);
+    double* tw = (double*)malloc(sizeof(double) * 2 * N);
+    if (!cell || !g || !taps || !tw) { free(cell); free(g); free(taps); free(tw); return ORA_E_NOMEM; }
+    rc = ora_geometry(s, cell, g);
+    if (rc == ORA_OK) rc = ora_taps(s, cell, g, taps);
+    if (rc != ORA_OK) { free(cell); free(g); free(taps); free(tw); return rc; }
+    twiddle_table(N, tw);
+
+    int nomem = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+#endif
+    for (int c = chan_begin; c < chan_end; ++c) {
+        double* grid = (double*)malloc(sizeof(double) * 2 * NN);
+        double* tmp = (double*)malloc(sizeof(double) * 2 * NN);
+        if (!grid || !tmp) {
+            free(grid); free(tmp);
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            nomem = 1;
+            continue;
+        }
+        const double* taps_c = taps + (size_t)c * A * P * K * K * 2;
+        const int32_t* cell_c = cell + (size_t)c * A * 2;
+        for (int64_t t = 0; t < T; ++t) {
+            const uint8_t* row = samples + ((size_t)t * C + c) * (size_t)A * P;
+            for (int p = 0; p < P; ++p) {
+                ora_grid(s, taps_c, cell_c, row, p, grid);
+                dft2(N, tw, grid, tmp, out + (((size_t)t * C + c) * P + p) * 2 * NN);
+            }
+        }
+        free(grid); free(tmp);
+    }
+    free(cell); free(g); free(taps); free(tw);
+    return nomem ? ORA_E_NOMEM : ORA_OK;
+}
+
 int ora_image(const ora_array* s, const uint8_t* samples, int64_t T, double* out, int n_threads) {
     if (!s) return ORA_E_ARG;
     return ora_image_range(s, samples, T, 0, s->n_chan, out, n_threads);

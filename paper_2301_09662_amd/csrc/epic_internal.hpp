@@ -109,7 +109,8 @@ hipError_t launch_entry_weights(const SubDev& d, hipStream_t st);
 // The FP32 hot path for one sub-array: n_time spectra of uint8 [T][C][A][P].
 // fp32_configure picks the launch shape; with device < 0 it makes no HIP call.
 hipError_t fp32_configure(SubDev& d, int device, int num_cu);
-hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
+hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st,
+                       float* efield = nullptr);
 
 // The FP16 matrix-core hot path (same contract as launch_fp32).
 hipError_t mfma_configure(SubDev& d, int device, int num_cu);

@@ -46,6 +46,7 @@ struct Fp32Args {
     const float4* grp_w;      // weights per group (1, 2 or 4 float4)
     const float2* twiddle;    // [N]
     float* slots;             // [S][C][NPP][N][N]
+    float2* efield;           // E-field form: [T][C][P][N][N] output images
     int Rmax, WP, YP;
     uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
     int nibble_order;
@@ -110,7 +111,9 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
     for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], tw[n1]);   // tw[0] = 1
 }
 
-template <int N_, int P, bool REAL, bool PROG_LDS>
+// EF: write each spectrum's transformed fields (X, Y) to a.efield instead of
+// accumulating their products.
+template <int N_, int P, bool REAL, bool PROG_LDS, bool EF = false>
 __global__ void __launch_bounds__(Shape<N_>::THREADS)
     __attribute__((amdgpu_waves_per_eu(Shape<N_>::MIN_WAVES_PER_EU))) fp32_kernel(Fp32Args a) {
     using Sh = Shape<N_>;
@@ -290,8 +293,34 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 }
             }
 
+            // 3b'. E-field form: each pixel's field, with the phase that moves the
+            //      window from the grid origin back to its cells, e^{+2 pi i (x0 kx + y0 ky)/N}
+            //      (the (-1)^(x+y) centring is the read of bin (i + N/2) mod N)
+            if constexpr (EF) {
+                if (lane_on) {
+                    const int kx = kpart * NK + kk;
+                    int ii = kx + N / 2;
+                    if (ii >= N) ii -= N;
+                    const int rx = (ci.x0 * kx) % N;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        float2 X[8];
+                        fold_twiddle<N>(X, s_Y + p * a.Rmax * a.YP + kk, a.YP, R, tw, s_tw, q);
+                        fft8(X);
+                        float2* out = a.efield + ((tt * a.C + c) * P + p) * (int64_t)N * N;
+#pragma unroll
+                        for (int m = 0; m < 8; ++m) {
+                            const int ky = q + Q * m;
+                            int jj = ky + N / 2;
+                            if (jj >= N) jj -= N;
+                            const float2 ph = s_tw[(rx + ci.y0 * ky) % N];
+                            out[jj * N + ii] = cmul(X[fft8_pos(m)], ph);
+                        }
+                    }
+                }
+            }
             // 3b + 4. column pass per pol, products and accumulation in registers
-            if (lane_on) {
+            if (!EF && lane_on) {
                 float2 X[8];
                 fold_twiddle<N>(X, s_Y + kk, a.YP, R, tw, s_tw, q);
                 fft8(X);
@@ -322,7 +351,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         }
 
         // add the segment's sums into its slot; bin (k', j') -> pixel (+N/2 mod N)
-        if (lane_on) {
+        if (!EF && lane_on) {
             const int kb = kpart * NK + kk;
             int ii = kb + N / 2;
             if (ii >= N) ii -= N;
@@ -371,18 +400,18 @@ Layout layout(const SubDev& d, int KS, bool prog_lds, int bufs) {
 
 using KernelFn = void (*)(Fp32Args);
 
-template <int N, int P>
+template <int N, int P, bool EF>
 KernelFn pick(bool real, bool prog) {
-    if (real) return prog ? fp32_kernel<N, P, true, true> : fp32_kernel<N, P, true, false>;
-    return prog ? fp32_kernel<N, P, false, true> : fp32_kernel<N, P, false, false>;
+    if (real) return prog ? fp32_kernel<N, P, true, true, EF> : fp32_kernel<N, P, true, false, EF>;
+    return prog ? fp32_kernel<N, P, false, true, EF> : fp32_kernel<N, P, false, false, EF>;
 }
 
 // Grid sizes with a kernel: multiples of 16 from 16 to 128.
-KernelFn select_kernel(int N, int P, bool real, bool prog) {
+KernelFn select_kernel(int N, int P, bool real, bool prog, bool ef = false) {
     switch (N * 2 + (P - 1)) {
-#define EPIC_CASE(NN)                                   \
-    case NN * 2 + 0: return pick<NN, 1>(real, prog);    \
-    case NN * 2 + 1: return pick<NN, 2>(real, prog);
+#define EPIC_CASE(NN)                                                                            \
+    case NN * 2 + 0: return ef ? pick<NN, 1, true>(real, prog) : pick<NN, 1, false>(real, prog); \
+    case NN * 2 + 1: return ef ? pick<NN, 2, true>(real, prog) : pick<NN, 2, false>(real, prog);
         EPIC_CASE(16) EPIC_CASE(32) EPIC_CASE(48) EPIC_CASE(64) EPIC_CASE(80) EPIC_CASE(96) EPIC_CASE(112)
         EPIC_CASE(128)
 #undef EPIC_CASE
@@ -455,7 +484,7 @@ hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
     return hipSuccess;
 }
 
-hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
+hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st, float* efield) {
     const bool prog = d.prog_lds != 0;
     const Layout L = layout(d, d.KS, prog, d.smp_bufs);
     Fp32Args a{};
@@ -467,6 +496,7 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.grp_ant = reinterpret_cast<const uint2*>(d.grp_ant);
     a.grp_w = reinterpret_cast<const float4*>(d.grp_w);
     a.twiddle = d.twiddle; a.slots = d.slots;
+    a.efield = reinterpret_cast<float2*>(efield);
     a.Rmax = d.Rmax; a.WP = d.WP; a.YP = L.YP;
     a.off_w = L.off_w; a.off_gant = L.off_gant; a.off_desc = L.off_desc;
     a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw;
@@ -474,8 +504,13 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.dbuf = d.smp_bufs == 2 ? 1 : 0;
     a.grid_wg = d.grid_wg;
     a.wg_per_xcd = (d.grid_wg + 7) / 8;
-    KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog);
+    KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog, efield != nullptr);
     if (!fn) return hipErrorNotSupported;
+    if (efield) {   // the E-field instances get their LDS limit on first use
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(d.threads), L.total, st, a);
     return hipGetLastError();
 }

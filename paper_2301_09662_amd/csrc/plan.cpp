@@ -585,6 +585,19 @@ epic_status epic_grid_fft_accumulate(epic_plan_t p, const uint8_t* const* d_samp
     return check_device(p, e);
 }
 
+epic_status epic_efield(epic_plan_t p, int32_t sub, const uint8_t* d_samples, int64_t n_time, float* d_out,
+                        void* hip_stream) {
+    if (!valid_plan(p) || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
+    if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;
+    if (n_time < 0 || n_time > p->desc.max_time) return EPIC_E_ARG;
+    if (p->desc.precision != EPIC_FP32) return EPIC_E_UNSUPPORTED;
+    if (n_time == 0) return EPIC_OK;
+    if (!d_samples || !d_out) return EPIC_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
+    return check_device(p, launch_fp32(p->subs[sub].dev, d_samples, n_time, st, d_out));
+}
+
 epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, void* hip_stream) {
     if (!valid_plan(p)) return EPIC_E_ARG;
     if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;

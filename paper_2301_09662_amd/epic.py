@@ -71,6 +71,7 @@ _lib.epic_plan.argtypes = [_P(epic_plan_desc), _vp, _P(_vp)]
 _lib.epic_grid_fft_accumulate.argtypes = [_vp, _P(_vp), ctypes.c_int64, _vp]
 _lib.epic_readout.argtypes = [_vp, _P(_vp), ctypes.c_int32, _vp]
 _lib.epic_set_gains.argtypes = [_vp, ctypes.c_int32, _P(ctypes.c_float), _vp]
+_lib.epic_efield.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]
 _lib.epic_plan_query.argtypes = [_vp, _P(epic_plan_info)]
 _lib.epic_debug_geometry.argtypes = [_vp, ctypes.c_int32, _P(ctypes.c_int32)]
 _lib.epic_debug_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, _P(ctypes.c_int32), _P(ctypes.c_int32)]
@@ -79,11 +80,11 @@ _lib.epic_destroy.argtypes = [_vp]
 _lib.epic_status_str.argtypes = [ctypes.c_int]
 _lib.epic_status_str.restype = ctypes.c_char_p
 _lib.epic_abi_version.argtypes = []
-for _f in ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_plan_query",
+for _f in ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_efield", "epic_plan_query",
            "epic_debug_geometry", "epic_debug_schedule", "epic_debug_unpack", "epic_destroy", "epic_abi_version"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_plan_query",
+EXPORTED = ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_efield", "epic_plan_query",
             "epic_debug_geometry", "epic_debug_schedule", "epic_debug_unpack", "epic_destroy", "epic_status_str",
             "epic_abi_version")
 
@@ -210,6 +211,13 @@ def epic_set_gains(plan: Plan, sub: int, gains: Optional[np.ndarray], stream=Non
     g = None if gains is None else np.ascontiguousarray(np.asarray(gains, dtype=np.float32))
     ptr = _P(ctypes.c_float)() if g is None else g.ctypes.data_as(_P(ctypes.c_float))
     _check(_lib.epic_set_gains(plan, int(sub), ptr, _stream_handle(stream)), "epic_set_gains")
+
+
+def epic_efield(plan: Plan, sub: int, samples, n_time: int, out, stream=None):
+    """E-field images of sub-array ``sub``: ``out`` is a float32 device tensor
+    [n_time][C][P][N][N][2] (or a raw device address)."""
+    _check(_lib.epic_efield(plan, int(sub), _dev_ptr(samples), int(n_time), _dev_ptr(out), _stream_handle(stream)),
+           "epic_efield")
 
 
 def epic_plan_query(plan: Plan) -> dict:

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from fx_bruteforce import fx_image, unpack_int
+from fx_bruteforce import fx_image, kernel_images, unpack_int
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -230,6 +230,38 @@ def test_autocorr_is_sum_of_single_antenna_images():
     ref = fx_image(x1, cell, oracle.taps(sub1), sub1.grid_n) - fx_image(x1, cell, oracle.taps(sub1), sub1.grid_n,
                                                                           drop_auto=True)
     assert np.abs(oracle.autocorr(sub1, x1) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_efield_single_antenna_is_kernel_image():
+    """One antenna: its field image is E times its kernel transform K(i, j),
+    evaluated directly per pixel (independent of the gridding + DFT route)."""
+    import copy
+    sub = copy.copy(synth.shrink(synth.workload(2).subs[0], n_chan=2))
+    sub.ant_xy = sub.ant_xy[5:6]
+    x = synth.samples(synth.shrink(synth.workload(2).subs[0], n_chan=2), 3)[:, :, 5:6]
+    x = np.ascontiguousarray(x)
+    ef = oracle.efield(sub, x)
+    cell, _ = oracle.geometry(sub)
+    re, im = unpack_int(x)
+    for c in range(2):
+        kimg = kernel_images(cell[c], oracle.taps(sub)[c], sub.grid_n)   # [A=1][P][j][i]
+        for t in range(3):
+            for p in range(2):
+                e = re[t, c, 0, p] + 1j * im[t, c, 0, p]
+                assert np.abs(ef[t, c, p] - e * kimg[0, p]).max() <= 1e-12 * (np.abs(kimg[0, p]).max() * 12)
+
+
+def test_efield_products_sum_to_image():
+    """Summed over spectra, |X|^2, |Y|^2 and X Y* of the field images are the
+    four products of the (FX-pinned) image."""
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=32)
+    x = synth.samples(sub, 7)
+    ef = oracle.efield(sub, x)
+    img = oracle.image(sub, x)
+    X, Y = ef[:, :, 0], ef[:, :, 1]
+    ref = np.stack([(np.abs(X) ** 2).sum(0), (np.abs(Y) ** 2).sum(0), (X * np.conj(Y)).real.sum(0),
+                    (X * np.conj(Y)).imag.sum(0)], axis=1)
+    assert np.abs(img - ref).max() <= 1e-12 * np.abs(img).max()
 
 
 def test_parseval():
