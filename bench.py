@@ -190,7 +190,8 @@ def main():
         "config": {"workload": f"{wl.name}: " + "; ".join(
             f"{s.n_ant} ant x {s.n_pol} pol, {s.n_chan} ch, N={s.grid_n}, dl={s.grid_dl}" for s in subs)
             + f", T={T} spectra per step", "n_time": T, "precision": precision,
-            "plan": {k: info32[k] for k in ("batched", "autotuned", "graph", "weight", "slots", "lds_bytes")}},
+            "plan": {k: info32[k] for k in ("batched", "can_batch", "form_ms", "autotuned", "graph", "weight",
+                                            "slots", "lds_bytes")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": counter_traffic(precision, wl.name),
                      "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch,

@@ -73,8 +73,12 @@ enum {
     EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time */
     EPIC_F_DRY_RUN = 4u,          /* validate and size on the CPU; touch no device */
     EPIC_F_REMOVE_AUTOCORR = 8u,  /* subtract each antenna's own power term (a = b) at read-out */
-    EPIC_F_COMPLEX_WEIGHTS = 16u  /* gather with complex weights even if every tap is real, so that
+    EPIC_F_COMPLEX_WEIGHTS = 16u, /* gather with complex weights even if every tap is real, so that
                                      epic_set_gains may pass complex (phase) gains later */
+    EPIC_F_ONE_LAUNCH = 32u       /* several FP16 sub-arrays: always one persistent launch for all of
+                                     them (EPIC_E_UNSUPPORTED if their shapes cannot share it).
+                                     Without it they run as one launch per sub-array, unless
+                                     EPIC_F_AUTOTUNE times both forms and the single launch wins */
 };
 
 /*
@@ -140,6 +144,8 @@ typedef struct {
     int32_t weight[16];            /* batched: cost of one spectrum per sub-array */
     int32_t col_split[16];         /* KS: workgroups sharing one spectrum's image columns */
     int32_t workgroups[16];        /* persistent workgroups of the sub-array's launch */
+    int32_t can_batch;             /* 1 if the one-launch form exists for these sub-arrays */
+    double form_ms[2];             /* autotuner: probe call time, one launch / one per sub-array */
 } epic_plan_info;
 
 /*

@@ -66,6 +66,9 @@ struct MfmaArgs {
     int grid_wg, wg_per_xcd;
 };
 
+// Row padding (halfs) of the matrix-core operand buffers in LDS.
+constexpr int kPadH = 8;
+
 template <int N_, int KK_>
 struct MShape {
     static constexpr int N = N_;
@@ -77,8 +80,8 @@ struct MShape {
     static constexpr int IT = NK / 16;             // 16-column tiles per workgroup
     static constexpr int WAVES = N / 16;           // one wave per 16 image rows
     static constexpr int NT1 = 2 / KS;             // row-pass output tiles per wave
-    static constexpr int A1P = K2 + 8;             // LDS pitches (halfs)
-    static constexpr int B2P = K2 + 8;
+    static constexpr int A1P = K2 + kPadH;         // LDS pitches (halfs)
+    static constexpr int B2P = K2 + kPadH;
 };
 
 template <int N_>
@@ -466,8 +469,8 @@ Layout layout(const SubDev& d, bool prog_lds) {
     L.lm.off_desc = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.CellMax * 8) : 0;
     L.lm.off_smp = (uint32_t)take_aligned(b, (size_t)2 * d.A * d.P * sizeof(float2));
     L.lm.smp_stride = d.A * d.P;
-    L.lm.off_A1 = (uint32_t)take_aligned(b, (size_t)L.M1max * (K2 + 8) * 2);
-    L.lm.off_B2 = (uint32_t)take_aligned(b, (size_t)d.P * NK * (K2 + 8) * 2);
+    L.lm.off_A1 = (uint32_t)take_aligned(b, (size_t)L.M1max * (K2 + kPadH) * 2);
+    L.lm.off_B2 = (uint32_t)take_aligned(b, (size_t)d.P * NK * (K2 + kPadH) * 2);
     L.total = (b + 15) & ~(size_t)15;
     return L;
 }
@@ -616,8 +619,8 @@ hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, in
         gd = std::max(gd, (size_t)d.CellMax * 8);
         smp = std::max(smp, (size_t)d.A * d.P);
         const int K2 = 32 * d.KK;
-        a1 = std::max(a1, (size_t)m1max_of(d) * (K2 + 8) * 2);
-        b2 = std::max(b2, (size_t)d.P * (d.N / d.KS) * (K2 + 8) * 2);
+        a1 = std::max(a1, (size_t)m1max_of(d) * (K2 + kPadH) * 2);
+        b2 = std::max(b2, (size_t)d.P * (d.N / d.KS) * (K2 + kPadH) * 2);
     }
     auto lay = [&](bool prog, LdsMap& lm) {
         size_t b = 0;

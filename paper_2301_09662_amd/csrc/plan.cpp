@@ -24,8 +24,8 @@ namespace {
 
 constexpr double kC0 = 299792458.0;   // m/s
 constexpr uint32_t kMagic = 0x45504943u;  // 'EPIC'
-constexpr uint32_t kKnownFlags =
-    EPIC_F_GRAPH | EPIC_F_AUTOTUNE | EPIC_F_DRY_RUN | EPIC_F_REMOVE_AUTOCORR | EPIC_F_COMPLEX_WEIGHTS;
+constexpr uint32_t kKnownFlags = EPIC_F_GRAPH | EPIC_F_AUTOTUNE | EPIC_F_DRY_RUN | EPIC_F_REMOVE_AUTOCORR |
+                                 EPIC_F_COMPLEX_WEIGHTS | EPIC_F_ONE_LAUNCH;
 
 struct SubHost {
     epic_array_desc desc{};
@@ -52,8 +52,12 @@ struct epic_plan_s {
     epic_status sticky = EPIC_OK;
     std::vector<void*> allocations;
     int64_t device_bytes = 0;
-    // several FP16 sub-arrays in one persistent launch
+    // several FP16 sub-arrays: one persistent launch for all of them (batched)
+    // or one dedicated launch each; can_batch says the first form exists
+    int can_batch = 0;
     int batched = 0;
+    double form_ms[2] = {0.0, 0.0};   // autotuner: batched / dedicated call time
+    std::vector<SubDev> bdev;        // per sub-array: the batched form's launch shape
     BatchDev bd{};
     std::vector<int> weights;        // cost of one spectrum per sub-array
     std::vector<BatchSub> table;     // host copy of bd.table
@@ -255,13 +259,69 @@ int model_weight(const SubHost& h) {
     return (int)std::lround(4.0 * mfma + valu / 64.0) + 1;
 }
 
+// The batched form of a sub-array: its tables and buffers, with the batched
+// kernel's launch shape.
+SubDev batch_view(const SubDev& d, const SubDev& shape) {
+    SubDev b = d;
+    b.threads = shape.threads;
+    b.lds_bytes = shape.lds_bytes;
+    b.prog_lds = shape.prog_lds;
+    b.grid_wg = shape.grid_wg;
+    return b;
+}
+
+// Time of one accumulate call of Tn spectra in either form, on probe inputs
+// and scratch slots (milliseconds, best of three after a warm-up call).
+epic_status time_forms(epic_plan_s* p, hipStream_t st, int64_t Tn, const std::vector<const uint8_t*>& in,
+                       const std::vector<float*>& slots, BatchSub* table, double* t_batch, double* t_sep) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return EPIC_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return EPIC_E_DEVICE; }
+    const int n_sub = (int)p->subs.size();
+    std::vector<BatchSub> tab(p->table);
+    for (int s = 0; s < n_sub; ++s) tab[s].slots = slots[s];
+    epic_status rc = EPIC_OK;
+    if (hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(BatchSub), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = EPIC_E_DEVICE;
+    BatchDev bd = p->bd;
+    bd.table = table;
+    double best[2] = {1e30, 1e30};
+    for (int form = 0; form < 2 && rc == EPIC_OK; ++form) {
+        for (int rep = 0; rep < 4 && rc == EPIC_OK; ++rep) {
+            float ms = 0.f;
+            hipError_t e = hipEventRecord(e0, st);
+            if (e == hipSuccess) {
+                if (form == 0) {
+                    e = launch_batch(bd, in.data(), n_sub, Tn, st);
+                } else {
+                    for (int s = 0; s < n_sub && e == hipSuccess; ++s) {
+                        SubDev d = p->subs[s].dev;
+                        d.slots = slots[s];
+                        e = launch_mfma(d, in[s], Tn, st);
+                    }
+                }
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = EPIC_E_DEVICE; break; }
+            if (rep > 0) best[form] = std::min(best[form], (double)ms);
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *t_batch = best[0];
+    *t_sep = best[1];
+    return rc;
+}
+
 // Measure each sub-array's time per spectrum in the batched kernel, alone,
 // on all-zero input (the work does not depend on the sample values), and use
 // the ratios as the cost weights of the work split.  Each probe gives every
 // workgroup a few spectra; the time per spectrum is the slope between a
 // probe and one twice as long, which removes the launch and tail overheads.
 // The probes add into scratch slots, never into the plan's accumulators.
-epic_status autotune_batch(epic_plan_s* p, hipStream_t st) {
+epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
     const int n_sub = (int)p->subs.size();
     const int G = p->bd.grid_wg;
     std::vector<double> tau(n_sub, 0.0);
@@ -323,6 +383,40 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st) {
     if (hipMemcpyAsync(p->bd.table, p->table.data(), p->table.size() * sizeof(BatchSub), hipMemcpyHostToDevice,
                        st) != hipSuccess)
         return EPIC_E_DEVICE;
+    if (choose_form) {
+        // the faster of one batched launch and one dedicated launch per
+        // sub-array, timed on a call as long as the plan allows (up to 256)
+        const int64_t Tn = std::min<int64_t>(p->desc.max_time, 256);
+        std::vector<const uint8_t*> in(n_sub, nullptr);
+        std::vector<float*> slots(n_sub, nullptr);
+        BatchSub* table = nullptr;
+        double tb = 0.0, ts = 0.0;
+        epic_status r2 = EPIC_OK;
+        for (int s = 0; s < n_sub && r2 == EPIC_OK; ++s) {
+            const SubDev& d = p->subs[s].dev;
+            const size_t ib = (size_t)Tn * d.C * d.A * d.P;
+            int64_t S = std::max(choose_slots(d, Tn), choose_slots(p->bdev[s], Tn));
+            const size_t sb = (size_t)S * d.C * d.NPP * d.N * d.N * sizeof(float);
+            uint8_t* x = nullptr;
+            if (hipMalloc(&x, ib) != hipSuccess || hipMalloc(&slots[s], sb) != hipSuccess) r2 = EPIC_E_NOMEM;
+            in[s] = x;
+            if (r2 == EPIC_OK && (hipMemsetAsync(x, 0, ib, st) != hipSuccess ||
+                                  hipMemsetAsync(slots[s], 0, sb, st) != hipSuccess))
+                r2 = EPIC_E_DEVICE;
+        }
+        if (r2 == EPIC_OK && hipMalloc(&table, n_sub * sizeof(BatchSub)) != hipSuccess) r2 = EPIC_E_NOMEM;
+        if (r2 == EPIC_OK) r2 = time_forms(p, st, Tn, in, slots, table, &tb, &ts);
+        hipStreamSynchronize(st);
+        for (int s = 0; s < n_sub; ++s) {
+            if (in[s]) hipFree(const_cast<uint8_t*>(in[s]));
+            if (slots[s]) hipFree(slots[s]);
+        }
+        if (table) hipFree(table);
+        if (r2 != EPIC_OK) return r2;
+        p->batched = tb <= ts ? 1 : 0;
+        p->form_ms[0] = tb;
+        p->form_ms[1] = ts;
+    }
     p->autotuned = 1;
     return EPIC_OK;
 }
@@ -407,27 +501,32 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
     }
     for (SubHost& h : p->subs) h.dev.precision = desc->precision;
     if (desc->precision == EPIC_FP16 && desc->n_sub > 1) {
-        // one persistent launch for every sub-array when they share a kernel family
+        // the single persistent launch exists when the sub-arrays share a kernel family
         std::vector<SubDev> devs;
         for (SubHost& h : p->subs) devs.push_back(h.dev);
         hipError_t e = batch_configure(devs.data(), (int)devs.size(), p->bd, p->dry_run ? -1 : p->device, p->num_cu);
         if (e == hipSuccess) {
-            p->batched = 1;
-            for (size_t k = 0; k < devs.size(); ++k) p->subs[k].dev = devs[k];
+            p->can_batch = 1;
+            p->bdev = devs;
         } else if (e != hipErrorNotSupported) {
             return hip_status(e);
         }
+        if ((desc->flags & EPIC_F_ONE_LAUNCH) && !p->can_batch) return EPIC_E_UNSUPPORTED;
+        p->batched = (desc->flags & EPIC_F_ONE_LAUNCH) ? 1 : 0;
+    } else if (desc->flags & EPIC_F_ONE_LAUNCH) {
+        return EPIC_E_UNSUPPORTED;
     }
-    for (SubHost& h : p->subs) {
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        SubHost& h = p->subs[k];
         SubDev& d = h.dev;
-        if (!p->batched) {
-            hipError_t e = (d.precision == EPIC_FP32) ? fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu)
-                                                      : mfma_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
-            if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
-            if (e != hipSuccess) return hip_status(e);
-        }
+        hipError_t e = (d.precision == EPIC_FP32) ? fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu)
+                                                  : mfma_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
+        if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
+        if (e != hipSuccess) return hip_status(e);
+        // slots for whichever form runs (unused ones stay zero)
         d.S = choose_slots(d, desc->max_time);
-        p->weights.push_back(p->batched ? model_weight(h) : 1);
+        if (p->can_batch) d.S = std::max(d.S, choose_slots(p->bdev[k], desc->max_time));
+        p->weights.push_back(p->can_batch ? model_weight(h) : 1);
         // size checks (also in dry run)
         const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
         if (slot_bytes > 64.0 * (1ull << 30)) return EPIC_E_NOMEM;
@@ -480,16 +579,18 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if ((s = hip_status(hipMemsetAsync(d.lag, 0, nl * sizeof(float), st))) != EPIC_OK) return s;
         }
     }
-    if (p->batched) {
+    if (p->can_batch) {
+        // the batched form shares every table and buffer of the dedicated one
+        for (size_t k = 0; k < p->subs.size(); ++k) p->bdev[k] = batch_view(p->subs[k].dev, p->bdev[k]);
         p->table.clear();
-        for (size_t k = 0; k < p->subs.size(); ++k) p->table.push_back(batch_entry(p->subs[k].dev, p->weights[k]));
+        for (size_t k = 0; k < p->subs.size(); ++k) p->table.push_back(batch_entry(p->bdev[k], p->weights[k]));
         epic_status s = dalloc(p, &p->bd.table, p->table.size());
         if (s != EPIC_OK) return s;
         if ((s = hip_status(hipMemcpyAsync(p->bd.table, p->table.data(), p->table.size() * sizeof(BatchSub),
                                            hipMemcpyHostToDevice, st))) != EPIC_OK)
             return s;
         if (desc->flags & EPIC_F_AUTOTUNE) {
-            if ((s = autotune_batch(p, st)) != EPIC_OK) return s;
+            if ((s = autotune_batch(p, st, (desc->flags & EPIC_F_ONE_LAUNCH) == 0)) != EPIC_OK) return s;
         }
     }
     if (desc->flags & EPIC_F_GRAPH) {
@@ -674,17 +775,21 @@ epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
         info->npp[k] = (p->desc.output == EPIC_OUT_STOKES) ? 4 : d.NPP;
         info->slots[k] = d.S;
         info->window_max[k] = std::max(d.Rmax, d.Wmax);
-        info->threads[k] = d.threads;
-        info->lds_bytes[k] = (int64_t)d.lds_bytes;
+        const SubDev& run = p->batched ? p->bdev[k] : d;   // the launch shape in use
+        info->threads[k] = run.threads;
+        info->lds_bytes[k] = (int64_t)run.lds_bytes;
     }
     info->device_bytes = p->device_bytes;
     info->graph = (p->desc.flags & EPIC_F_GRAPH) ? 1 : 0;
     info->autotuned = p->autotuned;
     info->batched = p->batched;
+    info->can_batch = p->can_batch;
+    info->form_ms[0] = p->form_ms[0];
+    info->form_ms[1] = p->form_ms[1];
     for (size_t k = 0; k < p->subs.size(); ++k) {
         info->weight[k] = p->weights[k];
         info->col_split[k] = p->subs[k].dev.KS;
-        info->workgroups[k] = p->subs[k].dev.grid_wg;
+        info->workgroups[k] = p->batched ? p->bdev[k].grid_wg : p->subs[k].dev.grid_wg;
     }
     return EPIC_OK;
 }
@@ -692,7 +797,7 @@ epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
 epic_status epic_debug_schedule(epic_plan_t p, int32_t sub, int64_t n_time, int32_t* h_wg, int32_t* h_slot) {
     if (!valid_plan(p) || !h_wg || !h_slot || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
     if (n_time < 1 || n_time > p->desc.max_time) return EPIC_E_ARG;
-    const SubDev& d = p->subs[sub].dev;
+    const SubDev& d = p->batched ? p->bdev[sub] : p->subs[sub].dev;
     const int64_t n = (int64_t)d.C * d.KS * n_time;
     std::fill(h_wg, h_wg + n, -1);
     std::fill(h_slot, h_slot + n, -1);
@@ -720,7 +825,7 @@ epic_status epic_debug_schedule(epic_plan_t p, int32_t sub, int64_t n_time, int3
                     const int64_t v = f / n_time, t = f - v * n_time;
                     const int64_t len = std::min(k1 - f, n_time - t);
                     const int slot = slot_of(g, v, t, n_time, base, w, Lc);
-                    if (slot < 0 || slot >= d.S) return EPIC_E_STATE;
+                    if (slot < 0 || slot >= p->subs[sub].dev.S) return EPIC_E_STATE;
                     for (int64_t k = f; k < f + len; ++k) {
                         if (h_wg[k] != -1) return EPIC_E_STATE;
                         h_wg[k] = g;

@@ -31,6 +31,7 @@ EPIC_FP32, EPIC_FP16, EPIC_FP8 = 0, 1, 2
 EPIC_GRID_AUTO, EPIC_GRID_GATHER, EPIC_GRID_DENSE_GEMM, EPIC_GRID_BLOCK_GEMM = 0, 1, 2, 3
 EPIC_OUT_POL, EPIC_OUT_STOKES = 0, 1
 EPIC_F_GRAPH, EPIC_F_AUTOTUNE, EPIC_F_DRY_RUN, EPIC_F_REMOVE_AUTOCORR, EPIC_F_COMPLEX_WEIGHTS = 1, 2, 4, 8, 16
+EPIC_F_ONE_LAUNCH = 32
 PRECISIONS = {"fp32": EPIC_FP32, "fp16": EPIC_FP16, "fp8": EPIC_FP8}
 
 
@@ -62,7 +63,8 @@ class epic_plan_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("lds_bytes", ctypes.c_int64 * 16),
                 ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("weight", ctypes.c_int32 * 16), ("col_split", ctypes.c_int32 * 16),
-                ("workgroups", ctypes.c_int32 * 16)]
+                ("workgroups", ctypes.c_int32 * 16), ("can_batch", ctypes.c_int32),
+                ("form_ms", ctypes.c_double * 2)]
 
 
 _P = ctypes.POINTER
@@ -229,7 +231,8 @@ def epic_plan_query(plan: Plan) -> dict:
             "threads": list(info.threads[:n]), "device_bytes": int(info.device_bytes),
             "lds_bytes": list(info.lds_bytes[:n]), "graph": info.graph, "autotuned": info.autotuned,
             "batched": info.batched, "weight": list(info.weight[:n]), "col_split": list(info.col_split[:n]),
-            "workgroups": list(info.workgroups[:n])}
+            "workgroups": list(info.workgroups[:n]), "can_batch": info.can_batch,
+            "form_ms": list(info.form_ms)}
 
 
 def epic_debug_schedule(plan: Plan, sub: int, n_time: int):

@@ -40,7 +40,7 @@ def test_split_of_device_plans(E):
     as an error)."""
     for nchan, T in (((3, 2, 2), 10), ((2, 2, 1), 9), ((2, 1, 1), 7), ((1, 1, 1), 3), ((132, 64, 32), 250)):
         subs = [synth.shrink(s, n_chan=n) for s, n in zip(synth.workload(4).subs, nchan)]
-        plan = E.epic_plan(subs, precision="fp16", max_time=T)
+        plan = E.epic_plan(subs, precision="fp16", max_time=T, flags=E.EPIC_F_ONE_LAUNCH)
         try:
             info = E.epic_plan_query(plan)
             for k in range(3):
@@ -53,7 +53,7 @@ def test_split_of_device_plans(E):
 
 def test_batched_parity(E):
     subs, xs = uneven()
-    gpu, info = run_library(E, subs, xs, precision="fp16")
+    gpu, info = run_library(E, subs, xs, precision="fp16", flags=E.EPIC_F_ONE_LAUNCH)
     assert info["batched"] == 1 and info["n_sub"] == 3
     assert all(w >= 1 for w in info["weight"])
     for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
@@ -63,30 +63,44 @@ def test_batched_parity(E):
 
 def test_batched_matches_separate_plans(E):
     subs, xs = uneven(nchan=(2, 2, 1), T=9)
-    batched, _ = run_library(E, subs, xs, precision="fp16")
+    batched, info = run_library(E, subs, xs, precision="fp16", flags=E.EPIC_F_ONE_LAUNCH)
+    assert info["batched"] == 1
+    dedicated, info = run_library(E, subs, xs, precision="fp16")
+    assert info["batched"] == 0 and info["can_batch"] == 1
     for k, (s, x) in enumerate(zip(subs, xs)):
         (alone,), info = run_library(E, [s], [x], precision="fp16")
         assert info["batched"] == 0
         fro, mx = image_errors(batched[k], alone)
         assert fro.max() <= 1e-5 and mx.max() <= 1e-5, f"sub {k}: {fro.max():.2e} {mx.max():.2e}"
+        assert np.array_equal(dedicated[k], alone), f"sub {k}: a plan's dedicated launch is the one-sub-array launch"
 
 
 def test_batched_split_calls_and_single_spectrum(E):
     subs, xs = uneven(nchan=(2, 1, 1), T=7)
-    gpu, _ = run_library(E, subs, xs, precision="fp16", calls=[1, 4, 2])
+    gpu, _ = run_library(E, subs, xs, precision="fp16", calls=[1, 4, 2], flags=E.EPIC_F_ONE_LAUNCH)
     for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
         assert_parity(g, oracle.image(s, x), TOL, f"split calls sub {k}")
 
 
 def test_autotuned_split(E):
     subs, xs = uneven(nchan=(2, 2, 2), T=12)
-    gpu, info = run_library(E, subs, xs, precision="fp16", flags=E.EPIC_F_AUTOTUNE)
+    gpu, info = run_library(E, subs, xs, precision="fp16", flags=E.EPIC_F_AUTOTUNE | E.EPIC_F_ONE_LAUNCH)
     assert info["batched"] == 1 and info["autotuned"] == 1
     w = info["weight"]
     print("autotuned weights per spectrum (A, B, C):", w)
     assert min(w) >= 1 and min(w) == 1000   # measured times relative to the cheapest sub-array
     for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
         assert_parity(g, oracle.image(s, x), TOL, f"autotuned sub {k}")
+
+
+def test_autotuner_picks_the_faster_form(E):
+    subs, xs = uneven(nchan=(3, 2, 2), T=16)
+    gpu, info = run_library(E, subs, xs, precision="fp16", flags=E.EPIC_F_AUTOTUNE)
+    tb, ts = info["form_ms"]
+    print(f"autotuner: one launch {tb:.3f} ms, one per sub-array {ts:.3f} ms -> batched={info['batched']}")
+    assert tb > 0 and ts > 0 and info["batched"] == (1 if tb <= ts else 0)
+    for k, (s, x, g) in enumerate(zip(subs, xs, gpu)):
+        assert_parity(g, oracle.image(s, x), TOL, f"autotuned form, sub {k}")
 
 
 def test_mixed_pol_counts_run_separately(E):
@@ -103,20 +117,22 @@ def test_mixed_pol_counts_run_separately(E):
 
 def test_full_uneven_batch_sampled_channels(E):
     """The full uneven batch (132 / 64 / 32 channels, 250 spectra, one call,
-    autotuned) against the oracle on the first and last channel of each
-    sub-array."""
+    autotuned, graph replay) in both forms against the oracle on the first and
+    last channel of each sub-array."""
     wl = synth.workload(4)
     xs = [synth.samples(s, wl.n_time) for s in wl.subs]
-    gpu, info = run_library(E, wl.subs, xs, precision="fp16", flags=E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH)
-    assert info["batched"] == 1 and info["graph"] == 1
-    for k, (s, x, g) in enumerate(zip(wl.subs, xs, gpu)):
-        for c in (0, s.n_chan - 1):
-            ora = oracle.image(s, x, chans=range(c, c + 1))
-            fro, mx = assert_parity(g[c:c + 1], ora[c:c + 1], TOL, f"full batch sub {k} channel {c}")
+    ora = {(k, c): oracle.image(s, x, chans=range(c, c + 1))[c:c + 1]
+           for k, (s, x) in enumerate(zip(wl.subs, xs)) for c in (0, s.n_chan - 1)}
+    for flags in (E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH | E.EPIC_F_ONE_LAUNCH, E.EPIC_F_AUTOTUNE | E.EPIC_F_GRAPH):
+        gpu, info = run_library(E, wl.subs, xs, precision="fp16", flags=flags)
+        assert info["graph"] == 1
+        print(f"full batch, batched={info['batched']}, form_ms={info['form_ms']}")
+        for (k, c), ref in ora.items():
+            fro, mx = assert_parity(gpu[k][c:c + 1], ref, TOL, f"full batch sub {k} channel {c}")
             print(f"full batch sub {k} channel {c}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
 
 
-def _graph_vs_eager(E, subs, xs, precision, n_list):
+def _graph_vs_eager(E, subs, xs, precision, n_list, extra=0):
     """Run the same accumulate / readout sequence through an eager plan and a
     graph plan, with unrelated torch work between replays, and return both
     lists of read-out cubes."""
@@ -125,7 +141,7 @@ def _graph_vs_eager(E, subs, xs, precision, n_list):
     T = xs[0].shape[0]
     res = {}
     for flags in (0, E.EPIC_F_GRAPH):
-        plan = E.epic_plan(subs, precision=precision, max_time=T, flags=flags)
+        plan = E.epic_plan(subs, precision=precision, max_time=T, flags=flags | extra)
         try:
             info = E.epic_plan_query(plan)
             assert info["graph"] == (1 if flags else 0)
@@ -148,7 +164,7 @@ def _graph_vs_eager(E, subs, xs, precision, n_list):
 def test_graph_replay_batched_fp16(E):
     subs, xs = uneven(nchan=(2, 1, 1), T=8)
     # replays of one capture, then a different n_time (re-capture), then the first again
-    eager, graph = _graph_vs_eager(E, subs, xs, "fp16", [8, 8, 8, 5, 8])
+    eager, graph = _graph_vs_eager(E, subs, xs, "fp16", [8, 8, 8, 5, 8], E.EPIC_F_ONE_LAUNCH)
     for r, (a, b) in enumerate(zip(eager, graph)):
         for k in range(len(subs)):
             assert np.array_equal(a[k], b[k]), f"replay {r} sub {k} differs from the eager result"

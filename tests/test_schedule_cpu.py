@@ -50,13 +50,17 @@ def test_station_split(E, precision, n_time):
         E.epic_destroy(p)
 
 
+@pytest.mark.parametrize("one_launch", [True, False])
 @pytest.mark.parametrize("n_time", [1, 2, 3, 5, 17, 250])
-def test_uneven_batch_split(E, n_time):
+def test_uneven_batch_split(E, n_time, one_launch):
+    """Both forms of a plan of sub-arrays: one persistent launch for all of
+    them (cost-weighted split) and one dedicated launch each."""
     wl = synth.workload(4)
-    p = dry(E, wl.subs, "fp16", wl.n_time)
+    p = dry(E, wl.subs, "fp16", wl.n_time, flags=E.EPIC_F_ONE_LAUNCH if one_launch else 0)
     try:
         info = E.epic_plan_query(p)
-        assert info["batched"] == 1 and min(info["weight"]) >= 1
+        assert info["can_batch"] == 1 and info["batched"] == (1 if one_launch else 0)
+        assert min(info["weight"]) >= 1
         # the N=96 array has the most expensive spectra in the cost model
         assert info["weight"][2] == max(info["weight"])
         for k in range(3):
@@ -71,7 +75,7 @@ def test_heavy_spectra_get_one_owner_each(E):
     slot is the spectrum index, which must stay below the slot count even
     where max_time caps it."""
     subs = [synth.shrink(s, n_chan=1) for s in synth.workload(4).subs]
-    p = dry(E, subs, "fp16", 3)
+    p = dry(E, subs, "fp16", 3, flags=E.EPIC_F_ONE_LAUNCH)
     try:
         info = E.epic_plan_query(p)
         assert info["batched"] == 1 and max(info["slots"]) <= 3
@@ -88,6 +92,16 @@ def test_heavy_spectra_get_one_owner_each(E):
                     assert (slot == np.arange(n_time)[None, :]).all()
     finally:
         E.epic_destroy(p)
+
+
+def test_one_launch_refused_where_it_cannot_run(E):
+    a = synth.shrink(synth.workload(4).subs[1], n_chan=2)
+    b = synth.shrink(synth.workload(1).subs[0], n_chan=2)        # single pol: another kernel family
+    with pytest.raises(E.EpicError) as ei:
+        dry(E, [a, b], "fp16", 4, flags=E.EPIC_F_ONE_LAUNCH)
+    assert ei.value.status == E.EPIC_E_UNSUPPORTED
+    with pytest.raises(E.EpicError):
+        dry(E, [a], "fp32", 4, flags=E.EPIC_F_ONE_LAUNCH)
 
 
 def test_schedule_validates(E):
