@@ -47,4 +47,17 @@ __host__ __device__ inline int slot_of(int g, int64_t v, int64_t t, int64_t T, i
     return g - (int)((base + v * T * w) / Lc);
 }
 
+// Column-part-major split of a one-sub-array launch whose image columns are
+// split over KS workgroups per spectrum: workgroup g works on column part
+// g % KS, and the G / KS workgroups of each part split that part's C x T
+// (channel, spectrum) sequence in contiguous runs.  The KS parts of a channel
+// then run at the same time on neighbouring workgroups (the same XCD), which
+// share the channel's gather program in L2.  G must be a multiple of KS.
+struct PartSplit {
+    int kpart;   // column part of workgroup g
+    int gp;      // its index among the workgroups of that part
+    int Gp;      // workgroups per part
+};
+__host__ __device__ inline PartSplit part_split(int g, int G, int KS) { return PartSplit{g % KS, g / KS, G / KS}; }
+
 }  // namespace epic

@@ -128,10 +128,12 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
     if (g >= a.grid_wg) return;
     const int64_t T = a.T;
-    const int64_t total = (int64_t)a.C * KS * T;
-    const int64_t L = (total + a.grid_wg - 1) / a.grid_wg;
+    const PartSplit ps = part_split(g, a.grid_wg, KS);
+    const int kpart = ps.kpart;
+    const int64_t total = (int64_t)a.C * T;   // this column part's (channel, spectrum) sequence
+    const int64_t L = (total + ps.Gp - 1) / ps.Gp;
     int64_t f0, f1;
-    owned_range(g, L, 0, 1, total, &f0, &f1);
+    owned_range(ps.gp, L, 0, 1, total, &f0, &f1);
     if (f0 >= f1) return;
 
     extern __shared__ __align__(16) unsigned char smem[];
@@ -159,9 +161,9 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     const int nwords = AP >> 2;
 
     uint32_t pre[kPrefetch];   // the next spectrum's sample words, loaded ahead of use
-    auto prefetch = [&](int vv, int64_t tt) {
+    auto prefetch = [&](int vv, int64_t tt) {   // vv: channel
         const uint32_t* row4 =
-            reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + vv / KS) * AP);
+            reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + vv) * AP);
 #pragma unroll
         for (int k = 0; k < kPrefetch; ++k) {
             const int w = tid + k * THREADS;
@@ -198,15 +200,14 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         }
     };
 
-    int v = (int)(f0 / T);
+    int v = (int)(f0 / T);   // channel
     int64_t t = f0 - (int64_t)v * T;
     if (words) prefetch(v, t);
     for (int64_t f = f0; f < f1;) {
-        // one channel segment: spectra t .. t+n-1 of virtual channel v
+        // one channel segment: spectra t .. t+n-1 of channel v
         const int64_t n = (f1 - f < T - t) ? f1 - f : T - t;
-        const int c = v / KS;
-        const int kpart = v - c * KS;
-        const int slot = slot_of(g, v, t, T, 0, 1, L);
+        const int c = v;
+        const int slot = slot_of(ps.gp, v, t, T, 0, 1, L);
         const ChanInfo ci = a.chans[c];
         const int R = ci.R, W = ci.W, n_cell = ci.n_cell;
         const CellDesc* g_desc = a.cells_desc + ci.cell_off;

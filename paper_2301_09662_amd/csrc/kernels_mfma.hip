@@ -118,13 +118,16 @@ __device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int
     }
 }
 
-// Process spectra [k0, k1) (index v*T + t, v = virtual channel) of one
-// sub-array with TH threads; waves beyond N/16 only help with the decoding,
-// gathering and clearing.  The spectra's cost offsets are base + k*w in units
-// where one workgroup's share is Lc (slot choice in slot_of).
+// Process the spectra [k0, k1) of a sequence (index s*T + t) of one
+// sub-array with TH threads; sequence channel s is virtual channel
+// v = s * vstep + voff (channel v / KS, column part v % KS).  Waves beyond
+// N/16 only help with the decoding, gathering and clearing.  The spectra's
+// cost offsets are base + k*w in units where workgroup g's share is Lc
+// (slot choice in slot_of).
 template <int N_, int KK_, int P, bool REAL, int TH>
 __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, unsigned char* smem, int64_t T, int g,
-                                         int64_t k0, int64_t k1, int64_t base, int64_t w_cost, int64_t Lc) {
+                                         int64_t k0, int64_t k1, int64_t base, int64_t w_cost, int64_t Lc,
+                                         int vstep, int voff) {
     using Sh = MShape<N_, KK_>;
     constexpr int N = Sh::N, KK = Sh::KK, KPAD = Sh::KPAD, K2 = Sh::K2, KS = Sh::KS, NK = Sh::NK;
     constexpr int IT = Sh::IT, NT1 = Sh::NT1, A1P = Sh::A1P, B2P = Sh::B2P, WAVES = Sh::WAVES;
@@ -198,15 +201,16 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
         }
     };
 
-    int v = (int)(k0 / T);
-    int64_t t = k0 - (int64_t)v * T;
+    int s_ch = (int)(k0 / T);   // sequence channel
+    int64_t t = k0 - (int64_t)s_ch * T;
+    int v = s_ch * vstep + voff;
     if (words) prefetch(v, t);
     for (int64_t f = k0; f < k1;) {
         // one channel segment: spectra t .. t+n-1 of virtual channel v
         const int64_t n = (k1 - f < T - t) ? k1 - f : T - t;
         const int c = v / KS;
         const int kpart = v - c * KS;
-        const int slot = slot_of(g, v, t, T, base, w_cost, Lc);
+        const int slot = slot_of(g, s_ch, t, T, base, w_cost, Lc);
         const ChanInfo ci = sc.chans[c];
         const int n_cell = ci.n_cell;
         const int R4 = (ci.R + 3) & ~3;
@@ -250,7 +254,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
         decode(s_smp0, c, t);
         if (words && f + 1 < k1) {
             if (t + 1 < T) prefetch(v, t + 1);
-            else prefetch(v + 1, 0);
+            else prefetch(v + vstep, 0);
         }
         __syncthreads();
 
@@ -270,7 +274,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
                 decode(s_nxt, c, tt + 1);
                 if (words && f + i + 2 < k1) {
                     if (tt + 2 < T) prefetch(v, tt + 2);
-                    else prefetch(v + 1, 0);
+                    else prefetch(v + vstep, 0);
                 }
             }
             __syncthreads();
@@ -356,7 +360,8 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             }
         }
         f += n;
-        ++v;
+        ++s_ch;
+        v += vstep;
         t = 0;
     }
 }
@@ -368,13 +373,15 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
     const int b = blockIdx.x;
     const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
     if (g >= a.grid_wg) return;
-    const int64_t total = (int64_t)a.V * a.T;
-    const int64_t L = (total + a.grid_wg - 1) / a.grid_wg;
+    constexpr int KS = MShape<N_, KK_>::KS;
+    const PartSplit ps = part_split(g, a.grid_wg, KS);
+    const int64_t total = (int64_t)(a.V / KS) * a.T;   // this column part's (channel, spectrum) sequence
+    const int64_t L = (total + ps.Gp - 1) / ps.Gp;
     int64_t k0, k1;
-    owned_range(g, L, 0, 1, total, &k0, &k1);
+    owned_range(ps.gp, L, 0, 1, total, &k0, &k1);
     if (k0 >= k1) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    mfma_run<N_, KK_, P, REAL, mfma_threads<N_>()>(a.sc, a.lm, smem, a.T, g, k0, k1, 0, 1, L);
+    mfma_run<N_, KK_, P, REAL, mfma_threads<N_>()>(a.sc, a.lm, smem, a.T, ps.gp, k0, k1, 0, 1, L, KS, ps.kpart);
 }
 
 // ---- several sub-arrays in one persistent launch ---------------------------
@@ -429,7 +436,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchArgs a) {
             switch (bs.N * 8 + bs.KK) {
 #define EPIC_RUN(NN, KKK)                                                                           \
     case NN * 8 + KKK:                                                                              \
-        mfma_run<NN, KKK, P, REAL, kBatchThreads>(sc, a.lm, smem, a.T, g, k0, k1, base, w, Lc);     \
+        mfma_run<NN, KKK, P, REAL, kBatchThreads>(sc, a.lm, smem, a.T, g, k0, k1, base, w, Lc, 1, 0); \
         break;
                 EPIC_BATCH_SHAPES(EPIC_RUN)
 #undef EPIC_RUN

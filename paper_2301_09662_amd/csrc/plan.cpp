@@ -798,43 +798,60 @@ epic_status epic_debug_schedule(epic_plan_t p, int32_t sub, int64_t n_time, int3
     if (!valid_plan(p) || !h_wg || !h_slot || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
     if (n_time < 1 || n_time > p->desc.max_time) return EPIC_E_ARG;
     const SubDev& d = p->batched ? p->bdev[sub] : p->subs[sub].dev;
-    const int64_t n = (int64_t)d.C * d.KS * n_time;
+    const int KS = d.KS;
+    const int64_t n = (int64_t)d.C * KS * n_time;
     std::fill(h_wg, h_wg + n, -1);
     std::fill(h_slot, h_slot + n, -1);
-    // the launch that holds `sub`: all sub-arrays (batched) or this one alone
-    std::vector<int> members;
-    if (p->batched) {
-        for (int s = 0; s < (int)p->subs.size(); ++s) members.push_back(s);
-    } else {
-        members.push_back(sub);
-    }
-    int64_t total = 0;
-    for (int s : members) total += (int64_t)p->subs[s].dev.C * p->subs[s].dev.KS * n_time * p->weights[s];
+    const int S = p->subs[sub].dev.S;
+    // visit one piece (workgroup g, virtual channel v, spectra [t, t + len)) with slot `slot`
+    auto piece = [&](int g, int64_t v, int64_t t, int64_t len, int slot) -> bool {
+        if (slot < 0 || slot >= S) return false;
+        for (int64_t k = v * n_time + t; k < v * n_time + t + len; ++k) {
+            if (h_wg[k] != -1) return false;
+            h_wg[k] = g;
+            h_slot[k] = slot;
+        }
+        return true;
+    };
     const int G = d.grid_wg;
-    const int64_t Lc = (total + G - 1) / G;
-    for (int g = 0; g < G; ++g) {
-        int64_t base = 0;
-        for (int s : members) {
-            const SubDev& e = p->subs[s].dev;
-            const int64_t items = (int64_t)e.C * e.KS * n_time, w = p->weights[s];
-            int64_t k0, k1;
-            owned_range(g, Lc, base, w, items, &k0, &k1);
-            if (s == sub) {
-                // the kernels' segment walk: one piece per virtual channel
-                for (int64_t f = k0; f < k1;) {
-                    const int64_t v = f / n_time, t = f - v * n_time;
-                    const int64_t len = std::min(k1 - f, n_time - t);
-                    const int slot = slot_of(g, v, t, n_time, base, w, Lc);
-                    if (slot < 0 || slot >= p->subs[sub].dev.S) return EPIC_E_STATE;
-                    for (int64_t k = f; k < f + len; ++k) {
-                        if (h_wg[k] != -1) return EPIC_E_STATE;
-                        h_wg[k] = g;
-                        h_slot[k] = slot;
+    if (p->batched) {
+        // one launch for all sub-arrays: the cost-weighted sequence over virtual channels
+        int64_t total = 0;
+        for (size_t s = 0; s < p->subs.size(); ++s)
+            total += (int64_t)p->bdev[s].C * p->bdev[s].KS * n_time * p->weights[s];
+        const int64_t Lc = (total + G - 1) / G;
+        for (int g = 0; g < G; ++g) {
+            int64_t base = 0;
+            for (int s = 0; s < (int)p->subs.size(); ++s) {
+                const SubDev& e = p->bdev[s];
+                const int64_t items = (int64_t)e.C * e.KS * n_time, w = p->weights[s];
+                int64_t k0, k1;
+                owned_range(g, Lc, base, w, items, &k0, &k1);
+                if (s == sub) {
+                    for (int64_t f = k0; f < k1;) {   // the kernels' segment walk
+                        const int64_t v = f / n_time, t = f - v * n_time;
+                        const int64_t len = std::min(k1 - f, n_time - t);
+                        if (!piece(g, v, t, len, slot_of(g, v, t, n_time, base, w, Lc))) return EPIC_E_STATE;
+                        f += len;
                     }
-                    f += len;
                 }
+                base += items * w;
             }
-            base += items * w;
+        }
+    } else {
+        // one launch for this sub-array: column-part-major split
+        const int64_t total = (int64_t)d.C * n_time;
+        for (int g = 0; g < G; ++g) {
+            const PartSplit ps = part_split(g, G, KS);
+            const int64_t L = (total + ps.Gp - 1) / ps.Gp;
+            int64_t k0, k1;
+            owned_range(ps.gp, L, 0, 1, total, &k0, &k1);
+            for (int64_t f = k0; f < k1;) {
+                const int64_t c = f / n_time, t = f - c * n_time;
+                const int64_t len = std::min(k1 - f, n_time - t);
+                if (!piece(g, c * KS + ps.kpart, t, len, slot_of(ps.gp, c, t, n_time, 0, 1, L))) return EPIC_E_STATE;
+                f += len;
+            }
         }
     }
     for (int64_t k = 0; k < n; ++k)

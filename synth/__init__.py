@@ -180,7 +180,7 @@ def workload(cfg: int) -> Workload:
         xy = layout_jittered_square(lay, 2048, 300.0)
         s = SubArray("large", xy, 2, 256, 128, 1.0, 40e6, seed_key=key)
         s.sources = _sources(src, [1.0, 0.7, 0.5], 128, 1.0, True)
-        return Workload(5, "large-fp8", [s], 125, "fp8")
+        return Workload(5, "large-2048ant", [s], 125, "fp8")
     raise ValueError(f"unknown config {cfg}")
 
 
