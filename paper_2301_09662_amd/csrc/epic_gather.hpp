@@ -10,15 +10,30 @@
 
 namespace epic {
 
+// Gather weight modes: complex weights (re, im per pol), real weights per pol,
+// or one real weight shared by both pols (X and Y taps equal, the default
+// Gaussian kernel).
+constexpr int kWComplex = 0, kWReal = 1, kWShared = 2;
+
 // ---- gather gridding of one group of kGroup entries ------------------------
-template <int P, bool REAL>
+template <int P, int WM>
 __device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float4* __restrict__ w,
                                              const uint2 ia, const float2* __restrict__ smp) {
     const int a[4] = {(int)(ia.x & 0xFFFFu), (int)(ia.x >> 16), (int)(ia.y & 0xFFFFu), (int)(ia.y >> 16)};
     if constexpr (P == 2) {
         const float4* s4 = reinterpret_cast<const float4*>(smp);
         const float4 s0 = s4[a[0]], s1 = s4[a[1]], s2 = s4[a[2]], s3 = s4[a[3]];
-        if constexpr (REAL) {
+        if constexpr (WM == kWShared) {
+            const float4 ww = w[0];   // (w0, w1, w2, w3), both pols
+            gx.x = fmaf(ww.x, s0.x, gx.x); gx.y = fmaf(ww.x, s0.y, gx.y);
+            gy.x = fmaf(ww.x, s0.z, gy.x); gy.y = fmaf(ww.x, s0.w, gy.y);
+            gx.x = fmaf(ww.y, s1.x, gx.x); gx.y = fmaf(ww.y, s1.y, gx.y);
+            gy.x = fmaf(ww.y, s1.z, gy.x); gy.y = fmaf(ww.y, s1.w, gy.y);
+            gx.x = fmaf(ww.z, s2.x, gx.x); gx.y = fmaf(ww.z, s2.y, gx.y);
+            gy.x = fmaf(ww.z, s2.z, gy.x); gy.y = fmaf(ww.z, s2.w, gy.y);
+            gx.x = fmaf(ww.w, s3.x, gx.x); gx.y = fmaf(ww.w, s3.y, gx.y);
+            gy.x = fmaf(ww.w, s3.z, gy.x); gy.y = fmaf(ww.w, s3.w, gy.y);
+        } else if constexpr (WM == kWReal) {
             const float4 w01 = w[0], w23 = w[1];   // (w0x, w0y, w1x, w1y), (w2x, w2y, w3x, w3y)
             gx.x = fmaf(w01.x, s0.x, gx.x); gx.y = fmaf(w01.x, s0.y, gx.y);
             gy.x = fmaf(w01.y, s0.z, gy.x); gy.y = fmaf(w01.y, s0.w, gy.y);
@@ -39,7 +54,7 @@ __device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float
         }
     } else {
         const float2 s0 = smp[a[0]], s1 = smp[a[1]], s2 = smp[a[2]], s3 = smp[a[3]];
-        if constexpr (REAL) {
+        if constexpr (WM != kWComplex) {
             const float4 ww = w[0];
             gx.x = fmaf(ww.x, s0.x, gx.x); gx.y = fmaf(ww.x, s0.y, gx.y);
             gx.x = fmaf(ww.y, s1.x, gx.x); gx.y = fmaf(ww.y, s1.y, gx.y);
@@ -55,9 +70,14 @@ __device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float
     }
 }
 
-template <int P, bool REAL>
+template <int P, int WM>
 constexpr int group_f4() {   // float4 words of weights per group
-    return REAL ? (P == 2 ? 2 : 1) : (P == 2 ? 4 : 2);
+    return WM == kWComplex ? (P == 2 ? 4 : 2) : ((WM == kWReal && P == 2) ? 2 : 1);
+}
+
+// the same on the host; floats per entry = 4 * group_f4 / kGroup
+inline int group_f4_of(int P, int wm) {
+    return wm == kWComplex ? (P == 2 ? 4 : 2) : ((wm == kWReal && P == 2) ? 2 : 1);
 }
 
 }  // namespace epic

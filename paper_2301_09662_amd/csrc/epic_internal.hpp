@@ -49,14 +49,14 @@ struct SubDev {
     int Rmax, Wmax;      // largest window over channels
     int WP;              // LDS row pitch (float2) of the gridded window
     int Gmax, CellMax;   // largest group / non-empty cell count over channels
-    int real_taps;       // every tap (and gain) is real: one float per pol per entry
+    int wmode;           // gather weights: 0 complex, 1 real per pol, 2 real shared by both pols
     int grid_wg;         // resident workgroups of one launch (persistent)
     // tables
     ChanInfo* chans;          // [C]
     CellDesc* cells_desc;     // [sum n_cell]
     uint16_t* grp_ant;        // [sum n_grp * kGroup] antenna per entry (0 for padding)
     uint8_t* grp_tap;         // [sum n_grp * kGroup] tap dy*K+dx, 255 for padding
-    float* grp_w;             // [sum n_grp * kGroup][WF] entry weights, WF = P (real) or 2P
+    float* grp_w;             // [sum n_grp * kGroup][WF] entry weights, WF = 2P, P or 1 by wmode
     int32_t* cells;           // [C][A][2] nearest cell
     double* gfrac;            // [C][A][2] fractional cell coordinate
     float* taps;              // [C][A][P][K][K][2] FP32 taps (before gains)
@@ -94,7 +94,7 @@ struct BatchSub {
 // Launch state of a batched plan.
 struct BatchDev {
     BatchSub* table;          // device [n_sub]
-    int grid_wg, threads, kkmax, P, real, prog_lds, smp_stride;
+    int grid_wg, threads, kkmax, P, wmode, prog_lds, smp_stride;
     size_t lds_bytes;
     uint32_t off[6];
 };

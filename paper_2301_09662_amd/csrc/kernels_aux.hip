@@ -3,6 +3,7 @@
 // decoder.  FP64 appears only here, never on the per-spectrum path.
 #include "epic_internal.hpp"
 #include "epic_device.hpp"
+#include "epic_gather.hpp"
 
 namespace epic {
 
@@ -48,12 +49,13 @@ __global__ void twiddle_kernel(float2* __restrict__ tw, int N) {
 
 // Weight of every gather entry: the entry's tap times the antenna's gain,
 // complex product in FP64, rounded once.  Padding entries (tap 255) weigh 0.
-// Layout per entry: real taps -> P floats (re per pol); complex -> 2P floats.
+// Layout per entry by weight mode: complex -> 2P floats (re, im per pol);
+// real -> P floats (re per pol); shared -> 1 float (the X weight, equal to Y).
 // One thread per entry slot of one channel.
 __global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const uint16_t* __restrict__ grp_ant,
                                      const uint8_t* __restrict__ grp_tap, const float* __restrict__ taps,
                                      const float* __restrict__ gains, float* __restrict__ grp_w, int C, int A,
-                                     int P, int K, int real) {
+                                     int P, int K, int wm) {
     const int c = blockIdx.y;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
@@ -61,8 +63,8 @@ __global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const u
     if (e >= ci.n_grp * kGroup) return;
     const int64_t ge = (int64_t)ci.grp_off * kGroup + e;
     const int a = grp_ant[ge], tap = grp_tap[ge];
-    const int wf = real ? P : 2 * P;
-    for (int p = 0; p < P; ++p) {
+    const int wf = wm == kWComplex ? 2 * P : (wm == kWReal ? P : 1);
+    for (int p = 0; p < (wm == kWShared ? 1 : P); ++p) {
         double wr = 0.0, wi = 0.0;
         if (tap != 255) {
             const int64_t ti = ((((int64_t)c * A + a) * P + p) * K * K + tap) * 2;
@@ -76,7 +78,7 @@ __global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const u
                 wi = i;
             }
         }
-        if (real) {
+        if (wm != kWComplex) {
             grp_w[ge * wf + p] = (float)wr;
         } else {
             grp_w[ge * wf + 2 * p + 0] = (float)wr;
@@ -282,7 +284,7 @@ hipError_t launch_twiddles(const SubDev& d, hipStream_t st) {
 hipError_t launch_entry_weights(const SubDev& d, hipStream_t st) {
     const int bs = 256;
     entry_weights_kernel<<<dim3((d.Gmax * kGroup + bs - 1) / bs, d.C), dim3(bs), 0, st>>>(
-        d.chans, d.grp_ant, d.grp_tap, d.taps, d.gains, d.grp_w, d.C, d.A, d.P, d.K, d.real_taps);
+        d.chans, d.grp_ant, d.grp_tap, d.taps, d.gains, d.grp_w, d.C, d.A, d.P, d.K, d.wmode);
     return hipGetLastError();
 }
 

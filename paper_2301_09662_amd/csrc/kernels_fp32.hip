@@ -113,13 +113,13 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
 
 // EF: write each spectrum's transformed fields (X, Y) to a.efield instead of
 // accumulating their products.
-template <int N_, int P, bool REAL, bool PROG_LDS, bool EF = false>
+template <int N_, int P, int WM, bool PROG_LDS, bool EF = false>
 __global__ void __launch_bounds__(Shape<N_>::THREADS)
     __attribute__((amdgpu_waves_per_eu(Shape<N_>::MIN_WAVES_PER_EU))) fp32_kernel(Fp32Args a) {
     using Sh = Shape<N_>;
     constexpr int N = Sh::N, Q = Sh::Q, KS = Sh::KS, NK = Sh::NK, LANES = Sh::LANES, THREADS = Sh::THREADS;
     constexpr int NPP = (P == 2) ? 4 : 1;
-    constexpr int GF4 = group_f4<P, REAL>();
+    constexpr int GF4 = group_f4<P, WM>();
     const int tid = threadIdx.x;
 
     // Persistent, XCD-aware: consecutive runs (mostly the same channel) share
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                     const int gg = (int)d.y + j;
                     const uint2 ia = PROG_LDS ? s_gant[gg] : g_gant[gg];
                     const float4* w = PROG_LDS ? s_w + gg * GF4 : g_w + (int64_t)gg * GF4;
-                    gather_group<P, REAL>(gx, gy, w, ia, s_smp);
+                    gather_group<P, WM>(gx, gy, w, ia, s_smp);
                 }
                 s_G[off] = gx;
                 if constexpr (P == 2) s_G[a.Rmax * a.WP + off] = gy;
@@ -386,7 +386,7 @@ Layout layout(const SubDev& d, int KS, bool prog_lds, int bufs) {
         b += n;
         return (uint32_t)o;
     };
-    const int gf4 = d.real_taps ? (d.P == 2 ? 2 : 1) : (d.P == 2 ? 4 : 2);
+    const int gf4 = group_f4_of(d.P, d.wmode);
     L.YP = d.N / KS + 1;
     L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
     L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
@@ -401,18 +401,24 @@ Layout layout(const SubDev& d, int KS, bool prog_lds, int bufs) {
 
 using KernelFn = void (*)(Fp32Args);
 
+template <int N, int P, int WM, bool EF>
+KernelFn pick_wm(bool prog) {
+    return prog ? fp32_kernel<N, P, WM, true, EF> : fp32_kernel<N, P, WM, false, EF>;
+}
+
 template <int N, int P, bool EF>
-KernelFn pick(bool real, bool prog) {
-    if (real) return prog ? fp32_kernel<N, P, true, true, EF> : fp32_kernel<N, P, true, false, EF>;
-    return prog ? fp32_kernel<N, P, false, true, EF> : fp32_kernel<N, P, false, false, EF>;
+KernelFn pick(int wm, bool prog) {
+    if (wm == kWComplex) return pick_wm<N, P, kWComplex, EF>(prog);
+    if (wm == kWShared && P == 2) return pick_wm<N, P, kWShared, EF>(prog);
+    return pick_wm<N, P, kWReal, EF>(prog);
 }
 
 // Grid sizes with a kernel: multiples of 16 from 16 to 128.
-KernelFn select_kernel(int N, int P, bool real, bool prog, bool ef = false) {
+KernelFn select_kernel(int N, int P, int wm, bool prog, bool ef = false) {
     switch (N * 2 + (P - 1)) {
 #define EPIC_CASE(NN)                                                                            \
-    case NN * 2 + 0: return ef ? pick<NN, 1, true>(real, prog) : pick<NN, 1, false>(real, prog); \
-    case NN * 2 + 1: return ef ? pick<NN, 2, true>(real, prog) : pick<NN, 2, false>(real, prog);
+    case NN * 2 + 0: return ef ? pick<NN, 1, true>(wm, prog) : pick<NN, 1, false>(wm, prog); \
+    case NN * 2 + 1: return ef ? pick<NN, 2, true>(wm, prog) : pick<NN, 2, false>(wm, prog);
         EPIC_CASE(16) EPIC_CASE(32) EPIC_CASE(48) EPIC_CASE(64) EPIC_CASE(80) EPIC_CASE(96) EPIC_CASE(112)
         EPIC_CASE(128)
 #undef EPIC_CASE
@@ -470,7 +476,7 @@ hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
     d.prog_lds = prog ? 1 : 0;
     int occ = 2;
     if (device >= 0) {
-        KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog);
+        KernelFn fn = select_kernel(d.N, d.P, d.wmode, prog);
         if (!fn) return hipErrorNotSupported;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
@@ -505,7 +511,7 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.dbuf = d.smp_bufs == 2 ? 1 : 0;
     a.grid_wg = d.grid_wg;
     a.wg_per_xcd = (d.grid_wg + 7) / 8;
-    KernelFn fn = select_kernel(d.N, d.P, d.real_taps != 0, prog, efield != nullptr);
+    KernelFn fn = select_kernel(d.N, d.P, d.wmode, prog, efield != nullptr);
     if (!fn) return hipErrorNotSupported;
     if (efield) {   // the E-field instances get their LDS limit on first use
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),

@@ -94,10 +94,10 @@ __device__ __forceinline__ floatx4 mfma16(half8 a, half8 b, floatx4 c) {
 // Gather gridding of every non-empty window cell (FP32 sums), stored as the
 // FP16 row-pass operand: row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)].
 // The program pointers are all in LDS or all in global memory.
-template <int P, bool REAL, int KPAD, int A1P, int TH, typename DescP, typename AntP, typename WP_>
+template <int P, int WM, int KPAD, int A1P, int TH, typename DescP, typename AntP, typename WP_>
 __device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int n_cell,
                                              const float2* __restrict__ smp, int WP, int R4, _Float16* s_A1) {
-    constexpr int GF4 = group_f4<P, REAL>();
+    constexpr int GF4 = group_f4<P, WM>();
     for (int k = threadIdx.x; k < n_cell; k += TH) {
         const uint2 d = desc[k];
         const int off = (int)(d.x & 0xFFFFu);
@@ -105,7 +105,7 @@ __device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int
         float2 gx = make_float2(0.f, 0.f), gy = make_float2(0.f, 0.f);
         for (int j = 0; j < ng; ++j) {
             const int gg = (int)d.y + j;
-            gather_group<P, REAL>(gx, gy, wts + (int64_t)gg * GF4, gant[gg], smp);
+            gather_group<P, WM>(gx, gy, wts + (int64_t)gg * GF4, gant[gg], smp);
         }
         const int r = off / WP, w = off - r * WP;
         _Float16* dst = s_A1 + r * A1P + w;
@@ -124,7 +124,7 @@ __device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int
 // N/16 only help with the decoding, gathering and clearing.  The spectra's
 // cost offsets are base + k*w in units where workgroup g's share is Lc
 // (slot choice in slot_of).
-template <int N_, int KK_, int P, bool REAL, int TH>
+template <int N_, int KK_, int P, int WM, int TH>
 __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, unsigned char* smem, int64_t T, int g,
                                          int64_t k0, int64_t k1, int64_t base, int64_t w_cost, int64_t Lc,
                                          int vstep, int voff) {
@@ -132,7 +132,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
     constexpr int N = Sh::N, KK = Sh::KK, KPAD = Sh::KPAD, K2 = Sh::K2, KS = Sh::KS, NK = Sh::NK;
     constexpr int IT = Sh::IT, NT1 = Sh::NT1, A1P = Sh::A1P, B2P = Sh::B2P, WAVES = Sh::WAVES;
     constexpr int NPP = (P == 2) ? 4 : 1;
-    constexpr int GF4 = group_f4<P, REAL>();
+    constexpr int GF4 = group_f4<P, WM>();
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -266,9 +266,9 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             // 2. gather gridding (FP32), stored as the FP16 row-pass operand:
             //    row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)]
             if (prog)
-                gather_cells<P, REAL, KPAD, A1P, TH>(s_desc, s_gant, s_w, n_cell, s_smp, sc.WP, R4, s_A1);
+                gather_cells<P, WM, KPAD, A1P, TH>(s_desc, s_gant, s_w, n_cell, s_smp, sc.WP, R4, s_A1);
             else
-                gather_cells<P, REAL, KPAD, A1P, TH>(g_desc, g_gant, g_w, n_cell, s_smp, sc.WP, R4, s_A1);
+                gather_cells<P, WM, KPAD, A1P, TH>(g_desc, g_gant, g_w, n_cell, s_smp, sc.WP, R4, s_A1);
             // 1'. decode the next spectrum of this segment into the other buffer
             if (i + 1 < n) {
                 decode(s_nxt, c, tt + 1);
@@ -368,7 +368,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
 
 // One sub-array: persistent, equal contiguous runs of the (channel, spectrum)
 // sequence, XCD-aware (consecutive runs share an XCD's L2).
-template <int N_, int KK_, int P, bool REAL>
+template <int N_, int KK_, int P, int WM>
 __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
     const int b = blockIdx.x;
     const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
     owned_range(ps.gp, L, 0, 1, total, &k0, &k1);
     if (k0 >= k1) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    mfma_run<N_, KK_, P, REAL, mfma_threads<N_>()>(a.sc, a.lm, smem, a.T, ps.gp, k0, k1, 0, 1, L, KS, ps.kpart);
+    mfma_run<N_, KK_, P, WM, mfma_threads<N_>()>(a.sc, a.lm, smem, a.T, ps.gp, k0, k1, 0, 1, L, KS, ps.kpart);
 }
 
 // ---- several sub-arrays in one persistent launch ---------------------------
@@ -406,7 +406,7 @@ struct BatchArgs {
     F(32, 1) F(32, 2) F(48, 1) F(48, 2) F(48, 3) F(64, 1) F(64, 2) F(64, 3) F(64, 4)      \
     F(96, 1) F(96, 2) F(96, 3) F(96, 4)
 
-template <int P, bool REAL>
+template <int P, int WM>
 __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchArgs a) {
     const int b = blockIdx.x;
     const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchArgs a) {
             switch (bs.N * 8 + bs.KK) {
 #define EPIC_RUN(NN, KKK)                                                                           \
     case NN * 8 + KKK:                                                                              \
-        mfma_run<NN, KKK, P, REAL, kBatchThreads>(sc, a.lm, smem, a.T, g, k0, k1, base, w, Lc, 1, 0); \
+        mfma_run<NN, KKK, P, WM, kBatchThreads>(sc, a.lm, smem, a.T, g, k0, k1, base, w, Lc, 1, 0); \
         break;
                 EPIC_BATCH_SHAPES(EPIC_RUN)
 #undef EPIC_RUN
@@ -467,7 +467,7 @@ int m1max_of(const SubDev& d) { return (d.P * ((d.Rmax + 3) & ~3) + 15) / 16 * 1
 Layout layout(const SubDev& d, bool prog_lds) {
     Layout L{};
     size_t b = 0;
-    const int gf4 = d.real_taps ? (d.P == 2 ? 2 : 1) : (d.P == 2 ? 4 : 2);
+    const int gf4 = group_f4_of(d.P, d.wmode);
     const int K2 = 32 * d.KK;
     const int NK = d.N / ks_of(d.N);
     L.M1max = m1max_of(d);
@@ -485,15 +485,18 @@ Layout layout(const SubDev& d, bool prog_lds) {
 using KernelFn = void (*)(MfmaArgs);
 
 template <int N, int KK>
-KernelFn pick2(int P, bool real) {
-    if (P == 2) return real ? mfma_kernel<N, KK, 2, true> : mfma_kernel<N, KK, 2, false>;
-    return real ? mfma_kernel<N, KK, 1, true> : mfma_kernel<N, KK, 1, false>;
+KernelFn pick2(int P, int wm) {
+    if (P == 2) {
+        if (wm == kWComplex) return mfma_kernel<N, KK, 2, kWComplex>;
+        return wm == kWShared ? mfma_kernel<N, KK, 2, kWShared> : mfma_kernel<N, KK, 2, kWReal>;
+    }
+    return wm == kWComplex ? mfma_kernel<N, KK, 1, kWComplex> : mfma_kernel<N, KK, 1, kWReal>;
 }
 
 // Grid sizes 32..128 (multiples of 16, not 80 / 112) with window depth KK*16 <= min(N, 64).
-KernelFn select_kernel(int N, int KK, int P, bool real) {
+KernelFn select_kernel(int N, int KK, int P, int wm) {
     switch (N * 8 + KK) {
-#define EPIC_K(NN, KKK) case NN * 8 + KKK: return pick2<NN, KKK>(P, real);
+#define EPIC_K(NN, KKK) case NN * 8 + KKK: return pick2<NN, KKK>(P, wm);
         EPIC_K(32, 1) EPIC_K(32, 2)
         EPIC_K(48, 1) EPIC_K(48, 2) EPIC_K(48, 3)
         EPIC_K(64, 1) EPIC_K(64, 2) EPIC_K(64, 3) EPIC_K(64, 4)
@@ -506,9 +509,12 @@ KernelFn select_kernel(int N, int KK, int P, bool real) {
 
 using BatchFn = void (*)(BatchArgs);
 
-BatchFn select_batch(int P, bool real) {
-    if (P == 2) return real ? batch_kernel<2, true> : batch_kernel<2, false>;
-    return real ? batch_kernel<1, true> : batch_kernel<1, false>;
+BatchFn select_batch(int P, int wm) {
+    if (P == 2) {
+        if (wm == kWComplex) return batch_kernel<2, kWComplex>;
+        return wm == kWShared ? batch_kernel<2, kWShared> : batch_kernel<2, kWReal>;
+    }
+    return wm == kWComplex ? batch_kernel<1, kWComplex> : batch_kernel<1, kWReal>;
 }
 
 bool batch_shape_ok(int N, int KK) {
@@ -561,7 +567,7 @@ hipError_t mfma_configure(SubDev& d, int device, int num_cu) {
     d.prog_lds = prog ? 1 : 0;
     int occ = 2;
     if (device >= 0) {
-        KernelFn fn = select_kernel(d.N, d.KK, d.P, d.real_taps != 0);
+        KernelFn fn = select_kernel(d.N, d.KK, d.P, d.wmode);
         if (!fn) return hipErrorNotSupported;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
@@ -600,7 +606,7 @@ hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.V = d.C * d.KS;
     a.grid_wg = d.grid_wg;
     a.wg_per_xcd = (d.grid_wg + 7) / 8;
-    KernelFn fn = select_kernel(d.N, d.KK, d.P, d.real_taps != 0);
+    KernelFn fn = select_kernel(d.N, d.KK, d.P, d.wmode);
     if (!fn) return hipErrorNotSupported;
     hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(d.threads), L.total, st, a);
     return hipGetLastError();
@@ -612,15 +618,15 @@ hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, 
 // catalogue with the same pol count and tap kind.  Fills bd (not the device
 // table, which the caller builds once slots and weights are known).
 hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, int num_cu) {
-    const int P = subs[0].P, real = subs[0].real_taps;
+    const int P = subs[0].P, wm = subs[0].wmode;
     size_t gw = 0, ga = 0, gd = 0, smp = 0, a1 = 0, b2 = 0;
     for (int s = 0; s < n_sub; ++s) {
         SubDev& d = subs[s];
-        if (d.P != P || d.real_taps != real) return hipErrorNotSupported;
+        if (d.P != P || d.wmode != wm) return hipErrorNotSupported;
         d.KK = (std::max(d.Rmax, d.Wmax) + 15) / 16;
         if (!batch_shape_ok(d.N, d.KK)) return hipErrorNotSupported;
         d.KS = ks_of(d.N);
-        const int gf4 = real ? (P == 2 ? 2 : 1) : (P == 2 ? 4 : 2);
+        const int gf4 = group_f4_of(P, wm);
         gw = std::max(gw, (size_t)d.Gmax * gf4 * 16);
         ga = std::max(ga, (size_t)d.Gmax * 8);
         gd = std::max(gd, (size_t)d.CellMax * 8);
@@ -652,12 +658,12 @@ hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, in
     bd.lds_bytes = total;
     bd.prog_lds = prog ? 1 : 0;
     bd.P = P;
-    bd.real = real;
+    bd.wmode = wm;
     bd.threads = kBatchThreads;
     bd.kkmax = 0;
     int occ = 1;
     if (device >= 0) {
-        BatchFn fn = select_batch(P, real != 0);
+        BatchFn fn = select_batch(P, wm);
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
         if (e != hipSuccess) return e;
@@ -705,7 +711,7 @@ hipError_t launch_batch(const BatchDev& bd, const uint8_t* const* samples, int n
     a.lm.off_w = bd.off[0]; a.lm.off_gant = bd.off[1]; a.lm.off_desc = bd.off[2];
     a.lm.off_smp = bd.off[3]; a.lm.off_A1 = bd.off[4]; a.lm.off_B2 = bd.off[5];
     a.lm.smp_stride = bd.smp_stride;
-    BatchFn fn = select_batch(bd.P, bd.real != 0);
+    BatchFn fn = select_batch(bd.P, bd.wmode);
     hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(kBatchThreads), bd.lds_bytes, st, a);
     return hipGetLastError();
 }

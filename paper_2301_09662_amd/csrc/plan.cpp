@@ -15,6 +15,7 @@
 #include <set>
 #include <vector>
 
+#include "epic_gather.hpp"
 #include "epic_internal.hpp"
 #include "epic_sched.hpp"
 
@@ -232,6 +233,21 @@ void free_all(epic_plan_s* p) {
         for (void* v : p->allocations) hipFree(v);
     }
     p->allocations.clear();
+}
+
+// Gather weight mode of a sub-array: complex when asked for or when any user
+// tap is complex; one weight shared by both pols when every X tap equals its
+// Y tap (always so for the default Gaussian); else real per pol.
+int weight_mode(const SubHost& h, uint32_t flags) {
+    if (flags & EPIC_F_COMPLEX_WEIGHTS) return kWComplex;
+    for (size_t k = 1; k < h.user_taps.size(); k += 2)
+        if (h.user_taps[k] != 0.0f) return kWComplex;
+    if (h.desc.n_pol != 2) return kWReal;
+    const size_t kk = (size_t)h.desc.kernel_k * h.desc.kernel_k * 2;   // floats per (c, a, p)
+    for (size_t base = 0; base < h.user_taps.size(); base += 2 * kk)
+        for (size_t k = 0; k < kk; ++k)
+            if (h.user_taps[base + k] != h.user_taps[base + kk + k]) return kWReal;
+    return kWShared;
 }
 
 // Slots per channel.  A launch runs grid_wg persistent workgroups, each taking
@@ -488,9 +504,7 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         SubDev& d = h.dev;
         d.A = h.desc.n_ant; d.P = h.desc.n_pol; d.C = h.desc.n_chan; d.N = h.desc.grid_n;
         d.K = h.desc.kernel_k; d.NPP = (d.P == 2) ? 4 : 1; d.nibble_order = h.desc.nibble_order;
-        d.real_taps = (desc->flags & EPIC_F_COMPLEX_WEIGHTS) ? 0 : 1;
-        for (size_t k = 1; k < h.user_taps.size(); k += 2)
-            if (h.user_taps[k] != 0.0f) { d.real_taps = 0; break; }
+        d.wmode = weight_mode(h, desc->flags);
     }
     if (!p->dry_run) {
         hipError_t e = hipSetDevice(p->device);
@@ -722,9 +736,14 @@ epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, voi
     if (h_gains) {
         for (size_t k = 0; k < n; ++k)
             if (!std::isfinite(h_gains[k])) return EPIC_E_ARG;
-        if (d.real_taps)
+        // real weights take real gains; weights shared by both pols also need
+        // equal X and Y gains (else the plan needs EPIC_F_COMPLEX_WEIGHTS)
+        if (d.wmode != kWComplex)
             for (size_t k = 1; k < n; k += 2)
-                if (h_gains[k] != 0.0f) return EPIC_E_UNSUPPORTED;   // needs EPIC_F_COMPLEX_WEIGHTS
+                if (h_gains[k] != 0.0f) return EPIC_E_UNSUPPORTED;
+        if (d.wmode == kWShared)
+            for (size_t k = 0; k < n; k += 4)
+                if (h_gains[k] != h_gains[k + 2]) return EPIC_E_UNSUPPORTED;
     }
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);

@@ -161,26 +161,37 @@ def test_gains_complex_and_reset_to_unit(E, precision, tol):
     assert_parity(o2[0], oracle.image(sub, x), tol, "unit gains again")
 
 
-def test_real_gains_on_real_plan_and_complex_refused(E):
+def test_real_gains_and_refusals(E):
+    """Real-weight plans take real gains: equal X and Y gains where one weight
+    serves both pols (the default kernel), per-pol gains where the taps differ
+    per pol; complex gains, or unequal ones on shared weights, are refused."""
     sub = synth.shrink(synth.workload(2).subs[0], n_chan=1, n_ant=64)
     x = synth.samples(sub, 6)
+    rng = np.random.default_rng(14)
     g = np.zeros((1, 64, 2, 2), dtype=np.float32)
-    g[..., 0] = np.random.default_rng(14).uniform(0.5, 2.0, (1, 64, 2))
+    g[..., 0, 0] = rng.uniform(0.5, 2.0, (1, 64))
+    g[..., 1, 0] = g[..., 0, 0]                                   # equal per pol
     (o,) = run_plan(E, [sub], [("gains", 0, g), ("acc", [x]), ("read", 1)])
     taps = user_taps(oracle.taps(sub))
-    assert_parity(o[0], oracle.image(sub, x, taps=gained_taps(sub, taps, g)), 1e-5, "real gains")
-    torch, dev = torch_dev()
+    assert_parity(o[0], oracle.image(sub, x, taps=gained_taps(sub, taps, g)), 1e-5, "shared weights, real gains")
+    # per-pol real taps: per-pol real gains
+    t2 = taps.copy()
+    t2[:, :, 1, ..., 0] *= 0.75                                   # Y taps differ from X
+    g2 = g.copy()
+    g2[..., 1, 0] = rng.uniform(0.5, 2.0, (1, 64))
+    (o2,) = run_plan(E, [sub], [("gains", 0, g2), ("acc", [x]), ("read", 1)], taps=[t2])
+    assert_parity(o2[0], oracle.image(sub, x, taps=gained_taps(sub, t2, g2)), 1e-5, "per-pol weights, real gains")
     plan = E.epic_plan([sub], max_time=6)
     try:
-        gc = g.copy()
-        gc[0, 0, 0, 1] = 0.5
-        with pytest.raises(E.EpicError) as ei:
-            E.epic_set_gains(plan, 0, gc)
-        assert ei.value.status == E.EPIC_E_UNSUPPORTED
+        for bad in (g2, np.where(np.arange(2) == 1, 0.5, g)):   # unequal per pol; a complex part
+            with pytest.raises(E.EpicError) as ei:
+                E.epic_set_gains(plan, 0, np.ascontiguousarray(bad, dtype=np.float32))
+            assert ei.value.status == E.EPIC_E_UNSUPPORTED
         gn = g.copy()
         gn[0, 1, 1, 0] = np.nan
-        with pytest.raises(E.EpicError):
+        with pytest.raises(E.EpicError) as ei:
             E.epic_set_gains(plan, 0, gn)
+        assert ei.value.status == E.EPIC_E_ARG
     finally:
         E.epic_destroy(plan)
 
