@@ -75,6 +75,20 @@ def counter_traffic(precision, workload):
     return entry["bytes_per_launch"]
 
 
+def rel_image_errors(img, ref):
+    """Per-image relative Frobenius error [C][NPP] of img against ref; the
+    cross products are normalised by sqrt(|XX| |YY|) of ref."""
+    C, npp = ref.shape[:2]
+    out = np.zeros((C, npp))
+    for c in range(C):
+        nx = np.linalg.norm(ref[c, 0])
+        ny = np.linalg.norm(ref[c, 1]) if npp == 4 else nx
+        for k in range(npp):
+            den = np.linalg.norm(ref[c, k]) if k < 2 else np.sqrt(nx * ny)
+            out[c, k] = np.linalg.norm(img[c, k] - ref[c, k]) / max(den, 1e-300)
+    return out
+
+
 def cpu_baseline(sub, samples, budget_s=15.0):
     """Time the FP64 oracle on a bounded sample of the same workload: all
     channels over the first T_s spectra, T_s sized for ~budget_s of wall time."""
@@ -201,25 +215,21 @@ def main():
         # matrix-core form: MFMA peak for context; the kernel is issue bound
         # on its vector work (gathering, FP16 packing, products)
         res["roofline"].update({"bound": "alu", "peak_fp16_mfma_tflops": FP16_MFMA_PEAK_TFLOPS})
-    if not args.no_reduced and precision == "fp32":
-        ms16, kern16, img16, info16 = run("fp16", args.steps, args.warmup)
-        # error of the FP16 form per image against the FP32 result (all channels)
-        # and against the FP64 oracle (two sampled channels)
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from gpu_util import image_errors
-        errs = [image_errors(a, b)[0].max() for a, b in zip(img16, img32)]
+    red_form = not args.no_reduced and precision == "fp32"
+    if red_form:
+        try:
+            ms16, kern16, img16, info16 = run("fp16", args.steps, args.warmup)
+        except E.EpicError as err:   # no matrix-core kernel for this grid size
+            res["reduced_precision"] = {"precision": "fp16", "unavailable": str(err)}
+            red_form = False
+    if red_form:
+        # error of the FP16 form per image against the FP32 result (all channels);
+        # its parity with the FP64 oracle is the tests' business
+        errs = [rel_image_errors(a, b).max() for a, b in zip(img16, img32)]
         red = {"precision": "fp16", "value": samples_per_step / (ms16 * 1e-3), "ms_per_step": ms16,
                "kernel_ms": kern16, "speedup_vs_fp32": ms_per_step / ms16,
                "max_rel_image_err_vs_fp32_all_channels": float(max(errs)),
                "achieved_algorithmic_tflops": flops_per_launch / (kern16 * 1e-3) / 1e12}
-        if not args.no_cpu_baseline:
-            import oracle
-            e_or = []
-            for c in (0, subs[0].n_chan - 1):
-                ora = oracle.image(subs[0], host[0], chans=range(c, c + 1))
-                e_or.append(float(image_errors(img16[0][c:c + 1], ora[c:c + 1])[0].max()))
-            red["max_rel_image_err_vs_oracle_sampled"] = max(e_or)
-            red["oracle_sampled_channels"] = [0, subs[0].n_chan - 1]
         res["reduced_precision"] = red
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(subs[0], host[0])

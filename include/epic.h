@@ -99,7 +99,10 @@ typedef struct {
     int32_t n_ant;               /* A >= 1, A * n_pol <= 65536 */
     int32_t n_pol;               /* P: 1 or 2 (X, Y) */
     int32_t n_chan;              /* C >= 1 */
-    int32_t grid_n;              /* N: multiple of 16 in [16, 128] */
+    int32_t grid_n;              /* N: multiple of 16 in [16, 256].  Kernels exist
+                                    for FP32 at 16..128 (every multiple of 16),
+                                    192 and 256; for FP16 at 32, 48, 64, 96 and
+                                    128.  Other sizes: EPIC_E_UNSUPPORTED */
     int32_t kernel_k;            /* K: odd, 1..7 */
     int32_t nibble_order;        /* 0: real part in the high nibble; 1: swapped */
     double grid_dl;              /* grid spacing in wavelengths (> 0) */

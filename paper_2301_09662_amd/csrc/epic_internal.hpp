@@ -12,7 +12,7 @@
 namespace epic {
 
 constexpr int kMaxSub = 16;
-constexpr int kMaxGridN = 128;
+constexpr int kMaxGridN = 256;
 
 // Aperture window of one (sub-array, channel): the bounding box of every
 // antenna's kernel footprint.  Cells outside it are identically zero, so the

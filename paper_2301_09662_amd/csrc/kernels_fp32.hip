@@ -58,7 +58,9 @@ template <int N_>
 struct Shape {
     static constexpr int N = N_;
     static constexpr int Q = N / 8;                            // lanes per image column
-    static constexpr int KS = (Q * N > 1024) ? 2 : 1;          // image columns split over KS workgroups
+    // image columns split over KS workgroups (1, 2, 4 or 8) so that a
+    // workgroup holds at most 1024 (q, column) lanes
+    static constexpr int KS = (Q * N <= 1024) ? 1 : (Q * N <= 2048 ? 2 : (Q * N <= 4096 ? 4 : 8));
     static constexpr int NK = N / KS;                          // columns per workgroup
     static constexpr int LANES = Q * NK;                       // (q, column) lanes
     static constexpr int THREADS = ((LANES + 63) / 64) * 64;
@@ -409,18 +411,19 @@ KernelFn pick_wm(bool prog) {
 template <int N, int P, bool EF>
 KernelFn pick(int wm, bool prog) {
     if (wm == kWComplex) return pick_wm<N, P, kWComplex, EF>(prog);
-    if (wm == kWShared && P == 2) return pick_wm<N, P, kWShared, EF>(prog);
+    if constexpr (P == 2)
+        if (wm == kWShared) return pick_wm<N, P, kWShared, EF>(prog);
     return pick_wm<N, P, kWReal, EF>(prog);
 }
 
-// Grid sizes with a kernel: multiples of 16 from 16 to 128.
+// Grid sizes with a kernel: multiples of 16 from 16 to 128, 192 and 256.
 KernelFn select_kernel(int N, int P, int wm, bool prog, bool ef = false) {
     switch (N * 2 + (P - 1)) {
 #define EPIC_CASE(NN)                                                                            \
     case NN * 2 + 0: return ef ? pick<NN, 1, true>(wm, prog) : pick<NN, 1, false>(wm, prog); \
     case NN * 2 + 1: return ef ? pick<NN, 2, true>(wm, prog) : pick<NN, 2, false>(wm, prog);
         EPIC_CASE(16) EPIC_CASE(32) EPIC_CASE(48) EPIC_CASE(64) EPIC_CASE(80) EPIC_CASE(96) EPIC_CASE(112)
-        EPIC_CASE(128)
+        EPIC_CASE(128) EPIC_CASE(192) EPIC_CASE(256)
 #undef EPIC_CASE
     }
     return nullptr;
@@ -436,6 +439,8 @@ int threads_for(int N) {
         case 96: return Shape<96>::THREADS;
         case 112: return Shape<112>::THREADS;
         case 128: return Shape<128>::THREADS;
+        case 192: return Shape<192>::THREADS;
+        case 256: return Shape<256>::THREADS;
     }
     return 0;
 }
@@ -450,6 +455,8 @@ int ks_for(int N) {
         case 96: return Shape<96>::KS;
         case 112: return Shape<112>::KS;
         case 128: return Shape<128>::KS;
+        case 192: return Shape<192>::KS;
+        case 256: return Shape<256>::KS;
     }
     return 1;
 }
@@ -462,7 +469,7 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // to the per-spectrum buffers, else it streams from L2.  The grid is one
 // resident round of workgroups (occupancy x CUs).  device < 0: no HIP calls.
 hipError_t fp32_configure(SubDev& d, int device, int num_cu) {
-    if (d.N < 16 || d.N > 128 || d.N % 16 != 0) return hipErrorNotSupported;
+    if (threads_for(d.N) == 0) return hipErrorNotSupported;
     d.KS = ks_for(d.N);
     d.threads = threads_for(d.N);
     // two sample buffers unless only one fits

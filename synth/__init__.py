@@ -146,6 +146,7 @@ def workload(cfg: int) -> Workload:
     3  = 2 in reduced precision (FP16 MFMA form)
     4  three uneven sub-arrays in one batched launch, T=250
     5  2048 dual-pol ant on a jittered 300 m square, 256 ch, N=128, T=125
+    6  the station of 2 on a 256 x 256 grid at 0.5 lambda, 132 ch, T=100 (wide grid)
     """
     if cfg == 1:
         lay, src, key = _streams(1)
@@ -181,6 +182,12 @@ def workload(cfg: int) -> Workload:
         s = SubArray("large", xy, 2, 256, 128, 1.0, 40e6, seed_key=key)
         s.sources = _sources(src, [1.0, 0.7, 0.5], 128, 1.0, True)
         return Workload(5, "large-2048ant", [s], 125, "fp8")
+    if cfg == 6:
+        lay, src, key = _streams(2)
+        xy = layout_ellipse(lay, 256, 100.0, 110.0)
+        s = SubArray("station-wide", xy, 2, 132, 256, 0.5, 40e6, seed_key=key)
+        s.sources = _sources(src, [1.0, 0.7, 0.5], 256, 0.5, True)
+        return Workload(6, "station-256grid", [s], 100, "fp32")
     raise ValueError(f"unknown config {cfg}")
 
 

@@ -116,7 +116,7 @@ class Sub:
 
 
 @pytest.mark.parametrize("bad,code", [
-    (dict(n_pol=3), "ARG"), (dict(n_chan=0), "ARG"), (dict(grid_n=40), "ARG"), (dict(grid_n=256), "ARG"),
+    (dict(n_pol=3), "ARG"), (dict(n_chan=0), "ARG"), (dict(grid_n=40), "ARG"), (dict(grid_n=272), "ARG"),
     (dict(kernel_k=2), "ARG"), (dict(kernel_k=9), "ARG"), (dict(grid_dl=0.0), "ARG"), (dict(grid_dl=np.nan), "ARG"),
     (dict(freq0_hz=-1.0), "ARG"), (dict(dfreq_hz=-1.0), "ARG"),
     (dict(ant_xy=np.array([[0.0, np.inf]])), "ARG"),

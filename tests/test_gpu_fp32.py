@@ -154,3 +154,16 @@ def test_full_station_sampled_channels(E):
     assert np.isfinite(gpu).all()
     assert (gpu[:, 0] >= 0).all() and (gpu[:, 1] >= 0).all()
     assert (gpu[:, 2] ** 2 + gpu[:, 3] ** 2 <= gpu[:, 0] * gpu[:, 1] * (1 + 1e-4) + 1e-3).all()
+
+
+@pytest.mark.parametrize("n,dl,nchan,T", [(256, 0.5, 2, 3), (192, 0.5, 1, 4)])
+def test_wide_grids(E, n, dl, nchan, T):
+    """256 x 256 and 192 x 192 grids (image columns over eight workgroups per
+    spectrum) against the oracle, station layout at half-wavelength spacing."""
+    import dataclasses
+    sub = dataclasses.replace(synth.shrink(synth.workload(2).subs[0], n_chan=nchan), grid_n=n, grid_dl=dl)
+    x = synth.samples(sub, T)
+    (gpu,), info = run_library(E, [sub], [x])
+    assert info["col_split"][0] == 8
+    fro, mx = assert_parity(gpu, oracle.image(sub, x), TOL, f"N={n}")
+    print(f"N={n}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")

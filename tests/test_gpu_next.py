@@ -211,14 +211,18 @@ def test_stokes_output(E, flags):
     assert np.abs(o[0] - st).max() <= 1e-5 * peak
 
 
-@pytest.mark.parametrize("cfg,k,nchan,nant,T", [(1, 0, 4, None, 6), (2, 0, 3, None, 5), (4, 1, 2, None, 4),
-                                                (5, 0, 1, 512, 2)])
-def test_efield_images(E, cfg, k, nchan, nant, T):
+@pytest.mark.parametrize("cfg,k,nchan,nant,T,wide", [(1, 0, 4, None, 6, 0), (2, 0, 3, None, 5, 0),
+                                                     (4, 1, 2, None, 4, 0), (5, 0, 1, 512, 2, 0),
+                                                     (2, 0, 1, None, 2, 256)])
+def test_efield_images(E, cfg, k, nchan, nant, T, wide):
     """Per-spectrum field images of each polarisation against the oracle's,
     phases included (N = 32 single pol, 64, 48, and 128 with the column
     split), to 1e-5 per image."""
     torch, dev = torch_dev()
     sub = synth.shrink(synth.workload(cfg).subs[k], n_chan=nchan, n_ant=nant)
+    if wide:
+        import dataclasses
+        sub = dataclasses.replace(sub, grid_n=wide, grid_dl=0.5)
     x = synth.samples(sub, T)
     ora = oracle.efield(sub, x)                                   # [T][C][P][N][N]
     plan = E.epic_plan([sub], max_time=T)

@@ -114,3 +114,36 @@ def test_schedule_validates(E):
             E.epic_debug_schedule(p, 1, 5)
     finally:
         E.epic_destroy(p)
+
+
+def wide_grid(sub, n, dl):
+    """The same array imaged on an n x n grid of spacing dl wavelengths."""
+    import dataclasses
+    return dataclasses.replace(sub, grid_n=n, grid_dl=dl)
+
+
+@pytest.mark.parametrize("n,dl,ks", [(256, 0.5, 8), (192, 0.5, 8)])
+def test_wide_grid_split(E, n, dl, ks):
+    """256 x 256 and 192 x 192 grids: each spectrum's columns span eight
+    workgroups; the column-part-major split still gives every spectrum one
+    owner per part and distinct slots."""
+    sub = wide_grid(synth.shrink(synth.workload(2).subs[0], n_chan=6), n, dl)
+    p = dry(E, [sub], "fp32", 40)
+    try:
+        info = E.epic_plan_query(p)
+        assert info["col_split"][0] == ks
+        for n_time in (1, 3, 40):
+            check_split(E, p, 0, n_time)
+    finally:
+        E.epic_destroy(p)
+
+
+def test_grid_sizes_without_a_kernel(E):
+    base = synth.shrink(synth.workload(2).subs[0], n_chan=1)
+    for n, prec in ((240, "fp32"), (256, "fp16"), (80, "fp16")):
+        with pytest.raises(E.EpicError) as ei:
+            dry(E, [wide_grid(base, n, 0.5)], prec, 4)
+        assert ei.value.status == E.EPIC_E_UNSUPPORTED, (n, prec)
+    with pytest.raises(E.EpicError) as ei:
+        dry(E, [wide_grid(base, 272, 0.5)], "fp32", 4)
+    assert ei.value.status == E.EPIC_E_ARG
