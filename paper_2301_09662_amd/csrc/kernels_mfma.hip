@@ -80,6 +80,10 @@ struct MShape {
     static constexpr int IT = NK / 16;             // 16-column tiles per workgroup
     static constexpr int WAVES = N / 16;           // one wave per 16 image rows
     static constexpr int NT1 = 2 / KS;             // row-pass output tiles per wave
+    // register budget: three waves per SIMD (168 VGPRs) for the small shapes,
+    // where the extra resident workgroup outweighs a few spills (measured:
+    // station N = 64, KK = 2: 0.75 -> 0.64 ms); the compiler's choice otherwise
+    static constexpr int WAVES_PER_EU = (N <= 64 && KK <= 2) ? 3 : 1;
     static constexpr int A1P = K2 + kPadH;         // LDS pitches (halfs)
     static constexpr int B2P = K2 + kPadH;
 };
@@ -369,7 +373,8 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
 // One sub-array: persistent, equal contiguous runs of the (channel, spectrum)
 // sequence, XCD-aware (consecutive runs share an XCD's L2).
 template <int N_, int KK_, int P, int WM>
-__global__ void __launch_bounds__(mfma_threads<N_>()) mfma_kernel(MfmaArgs a) {
+__global__ void __launch_bounds__(mfma_threads<N_>())
+__attribute__((amdgpu_waves_per_eu(MShape<N_, KK_>::WAVES_PER_EU))) mfma_kernel(MfmaArgs a) {
     const int b = blockIdx.x;
     const int g = (b & 7) * a.wg_per_xcd + (b >> 3);
     if (g >= a.grid_wg) return;
