@@ -221,16 +221,16 @@ epic_status upload(epic_plan_s* p, T** ptr, const std::vector<T>& v, hipStream_t
 
 void free_all(epic_plan_s* p) {
     if (!p->dry_run) {
-        hipSetDevice(p->device);
-        hipDeviceSynchronize();
-        if (p->gain_ev) hipEventDestroy(p->gain_ev);
-        if (p->gain_stage) hipHostFree(p->gain_stage);
+        (void)hipSetDevice(p->device);
+        (void)hipDeviceSynchronize();
+        if (p->gain_ev) (void)hipEventDestroy(p->gain_ev);
+        if (p->gain_stage) (void)hipHostFree(p->gain_stage);
         p->gain_ev = nullptr; p->gain_stage = nullptr;
-        if (p->exec) hipGraphExecDestroy(p->exec);
-        if (p->graph) hipGraphDestroy(p->graph);
-        if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
         p->exec = nullptr; p->graph = nullptr; p->cap_stream = nullptr;
-        for (void* v : p->allocations) hipFree(v);
+        for (void* v : p->allocations) (void)hipFree(v);
     }
     p->allocations.clear();
 }
@@ -292,7 +292,7 @@ epic_status time_forms(epic_plan_s* p, hipStream_t st, int64_t Tn, const std::ve
                        const std::vector<float*>& slots, BatchSub* table, double* t_batch, double* t_sep) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return EPIC_E_DEVICE;
-    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return EPIC_E_DEVICE; }
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return EPIC_E_DEVICE; }
     const int n_sub = (int)p->subs.size();
     std::vector<BatchSub> tab(p->table);
     for (int s = 0; s < n_sub; ++s) tab[s].slots = slots[s];
@@ -324,8 +324,8 @@ epic_status time_forms(epic_plan_s* p, hipStream_t st, int64_t Tn, const std::ve
             if (rep > 0) best[form] = std::min(best[form], (double)ms);
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *t_batch = best[0];
     *t_sep = best[1];
     return rc;
@@ -343,7 +343,7 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
     std::vector<double> tau(n_sub, 0.0);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return EPIC_E_DEVICE;
-    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return EPIC_E_DEVICE; }
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return EPIC_E_DEVICE; }
     epic_status rc = EPIC_OK;
     for (int s = 0; s < n_sub && rc == EPIC_OK; ++s) {
         const SubDev& d = p->subs[s].dev;
@@ -385,13 +385,13 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
             const double slope = (best[1] - best[0]) / (double)(V * (T2 - T1));
             tau[s] = slope > 0.0 ? slope : best[1] / (double)(V * T2);
         }
-        hipStreamSynchronize(st);
-        if (entry) hipFree(entry);
-        if (slots) hipFree(slots);
-        if (in) hipFree(in);
+        (void)hipStreamSynchronize(st);
+        if (entry) (void)hipFree(entry);
+        if (slots) (void)hipFree(slots);
+        if (in) (void)hipFree(in);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != EPIC_OK) return rc;
     const double tmin = *std::min_element(tau.begin(), tau.end());
     for (int s = 0; s < n_sub; ++s)
@@ -422,12 +422,12 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
         }
         if (r2 == EPIC_OK && hipMalloc(&table, n_sub * sizeof(BatchSub)) != hipSuccess) r2 = EPIC_E_NOMEM;
         if (r2 == EPIC_OK) r2 = time_forms(p, st, Tn, in, slots, table, &tb, &ts);
-        hipStreamSynchronize(st);
+        (void)hipStreamSynchronize(st);
         for (int s = 0; s < n_sub; ++s) {
-            if (in[s]) hipFree(const_cast<uint8_t*>(in[s]));
-            if (slots[s]) hipFree(slots[s]);
+            if (in[s]) (void)hipFree(const_cast<uint8_t*>(in[s]));
+            if (slots[s]) (void)hipFree(slots[s]);
         }
-        if (table) hipFree(table);
+        if (table) (void)hipFree(table);
         if (r2 != EPIC_OK) return r2;
         p->batched = tb <= ts ? 1 : 0;
         p->form_ms[0] = tb;
@@ -466,8 +466,8 @@ hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t 
 hipError_t launch_step_graph(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
     std::vector<const uint8_t*> ptrs(d_samples, d_samples + p->subs.size());
     if (!p->exec || p->graph_T != n_time || p->graph_ptrs != ptrs) {
-        if (p->exec) { hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-        if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+        if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
         hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
         hipError_t le = launch_step(p, d_samples, n_time, p->cap_stream);
@@ -764,7 +764,7 @@ epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, voi
             p->gain_ev_pending = 0;
         }
         if (p->gain_stage_n < n) {
-            if (p->gain_stage) hipHostFree(p->gain_stage);
+            if (p->gain_stage) (void)hipHostFree(p->gain_stage);
             p->gain_stage = nullptr;
             p->gain_stage_n = 0;
             if (hipHostMalloc(reinterpret_cast<void**>(&p->gain_stage), n * sizeof(float), hipHostMallocDefault) !=
