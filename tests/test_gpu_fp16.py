@@ -71,3 +71,20 @@ def test_full_station_sampled_channels(E):
         ora = oracle.image(sub, x, chans=range(c, c + 1))
         fro, mx = assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"cfg3 full, channel {c}")
         print(f"cfg3 channel {c}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+
+
+def test_degenerate_arrays_and_swapped_nibbles(E):
+    """One antenna; two antennas whose kernels touch cells 0 and N-1 (the
+    window spans the whole grid); nibble order 1 -- in the FP16 form."""
+    lam = 299792458.0 / 40e6
+
+    class S:
+        n_pol, n_chan, grid_n, grid_dl, freq0_hz, dfreq_hz, kernel_k = 2, 1, 32, 0.5, 40e6, 0.0, 3
+    edge = np.array([[-15 * 0.5 * lam, -15 * 0.5 * lam], [14 * 0.5 * lam, 14 * 0.5 * lam]])
+    for k, xy in enumerate((np.array([[1.3, -2.2]]), edge)):
+        s = S()
+        s.ant_xy = xy
+        x = np.random.default_rng(20 + k).integers(0, 256, (7, 1, len(xy), 2), dtype=np.uint8)
+        for order in (0, 1):
+            (gpu,), _ = run_library(E, [s], [x], precision="fp16", nibble_order=order)
+            assert_parity(gpu, oracle.image(s, x, nibble_order=order), TOL, f"fp16 edge{len(xy)} order{order}")

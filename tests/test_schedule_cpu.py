@@ -147,3 +147,16 @@ def test_grid_sizes_without_a_kernel(E):
     with pytest.raises(E.EpicError) as ei:
         dry(E, [wide_grid(base, 272, 0.5)], "fp32", 4)
     assert ei.value.status == E.EPIC_E_ARG
+
+
+def test_arrays_too_large_for_lds_are_refused(E):
+    """20000 dual-pol antennas need more LDS for one spectrum's decoded
+    samples than a workgroup has: the plan says so instead of launching."""
+    import dataclasses
+    base = synth.shrink(synth.workload(2).subs[0], n_chan=1)
+    rng = np.random.default_rng(1)
+    big = dataclasses.replace(base, ant_xy=rng.uniform(-40, 40, (20000, 2)))
+    for prec in ("fp32", "fp16"):
+        with pytest.raises(E.EpicError) as ei:
+            dry(E, [big], prec, 4)
+        assert ei.value.status == E.EPIC_E_UNSUPPORTED
