@@ -21,6 +21,11 @@
 // X and Y values in the same lane, so the products and the time accumulation
 // never leave registers: 8 pixels x 4 products per lane.
 //
+// Large grids split the image columns over KS workgroups by q: part k takes
+// q in [k Q/KS, (k+1) Q/KS), i.e. the columns j = q + Q m of those q, so each
+// part row-transforms only its own q values (the row pass is not repeated per
+// part; the decode and the gridding are).
+//
 // The window sits at the grid origin instead of at its absolute cells, and the
 // (-1)^(x+y) image-centring factor is replaced by reading bin (i + N/2) mod N
 // for pixel i: both only multiply X and Y by one common unit phase, which the
@@ -62,6 +67,8 @@ struct Shape {
     // workgroup holds at most 1024 (q, column) lanes
     static constexpr int KS = (Q * N <= 1024) ? 1 : (Q * N <= 2048 ? 2 : (Q * N <= 4096 ? 4 : 8));
     static constexpr int NK = N / KS;                          // columns per workgroup
+    static constexpr int QS = Q / KS;                          // row-pass q values per workgroup
+    static_assert(Q % KS == 0, "the column parts split q evenly");
     static constexpr int LANES = Q * NK;                       // (q, column) lanes
     static constexpr int THREADS = ((LANES + 63) / 64) * 64;
     // register budget: two 8-wave workgroups per CU (<= 128 VGPRs); larger
@@ -78,8 +85,9 @@ constexpr int kPrefetch = 1;   // sample words per thread held in registers ahea
 // whole blocks of 8, so the first block is a plain load and no block needs a
 // bounds check; when the last block's non-zero part fits in its first half,
 // only that half is folded.  Control flow depends only on len (uniform).
-// s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}.
-template <int N>
+// s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}, or with
+// TW_LDS the factors are read from s_tw (n1 q < 7 Q < N) and tw is unused.
+template <int N, bool TW_LDS = false>
 __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int stride, int len,
                                              const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
 #pragma unroll
@@ -110,7 +118,7 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
         }
     }
 #pragma unroll
-    for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], tw[n1]);   // tw[0] = 1
+    for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], TW_LDS ? s_tw[n1 * q] : tw[n1]);   // w^0 = 1
 }
 
 // EF: write each spectrum's transformed fields (X, Y) to a.efield instead of
@@ -157,6 +165,17 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     float2 tw[8];
 #pragma unroll
     for (int n1 = 0; n1 < 8; ++n1) tw[n1] = a.twiddle[(n1 * q) % N];
+    // row-pass lanes (qr, kr): this part's q values, N row slots each (with
+    // KS = 1 these are the column lanes (q, kk) again)
+    constexpr int QS = Sh::QS;
+    int qr = lane_on ? kpart * QS + tid / N : 0;
+    if constexpr (N % 64 == 0) qr = __builtin_amdgcn_readfirstlane(qr);
+    const int kr = lane_on ? tid % N : 0;
+    // image column of local column kk
+    auto column_of = [&](int k) {
+        if constexpr (KS == 1) return k;
+        return kpart * QS + k % QS + Q * (k / QS);
+    };
 
     const int AP = a.A * P;
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.samples) & 3) == 0);
@@ -270,18 +289,19 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             }
             __syncthreads();
 
-            // 3a. row pass: R rows per pol, outputs for this workgroup's columns
+            // 3a. row pass: R rows per pol, this part's q values; local
+            //     column qr - kpart QS + QS m holds image column qr + Q m
             if (lane_on) {
-                for (int rr = kk; rr < P * R; rr += NK) {
+                for (int rr = kr; rr < P * R; rr += N) {
                     const int p = (P == 2 && rr >= R) ? 1 : 0;
                     const int r = rr - p * R;
                     float2 z[8];
-                    fold_twiddle<N>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, s_tw, q);
+                    // with KS = 1, qr = q and tw holds its factors
+                    fold_twiddle<N, (KS > 1)>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, s_tw, qr);
                     fft8(z);
-                    float2* yrow = s_Y + (p * a.Rmax + r) * a.YP;
+                    float2* yrow = s_Y + (p * a.Rmax + r) * a.YP + (qr - kpart * QS);
 #pragma unroll
-                    for (int m = 0; m < 8; ++m)
-                        if ((m / (8 / KS)) == kpart) yrow[q + Q * m - kpart * NK] = z[fft8_pos(m)];
+                    for (int m = 0; m < 8; ++m) yrow[QS * m] = z[fft8_pos(m)];
                 }
             }
             __syncthreads();
@@ -301,7 +321,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             //      (the (-1)^(x+y) centring is the read of bin (i + N/2) mod N)
             if constexpr (EF) {
                 if (lane_on) {
-                    const int kx = kpart * NK + kk;
+                    const int kx = column_of(kk);
                     int ii = kx + N / 2;
                     if (ii >= N) ii -= N;
                     const int rx = (ci.x0 * kx) % N;
@@ -355,7 +375,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 
         // add the segment's sums into its slot; bin (k', j') -> pixel (+N/2 mod N)
         if (!EF && lane_on) {
-            const int kb = kpart * NK + kk;
+            const int kb = column_of(kk);
             int ii = kb + N / 2;
             if (ii >= N) ii -= N;
             float* base = a.slots + ((int64_t)slot * a.C + c) * NPP * N * N;

@@ -156,14 +156,16 @@ def test_full_station_sampled_channels(E):
     assert (gpu[:, 2] ** 2 + gpu[:, 3] ** 2 <= gpu[:, 0] * gpu[:, 1] * (1 + 1e-4) + 1e-3).all()
 
 
-@pytest.mark.parametrize("n,dl,nchan,T", [(256, 0.5, 2, 3), (192, 0.5, 1, 4)])
-def test_wide_grids(E, n, dl, nchan, T):
+@pytest.mark.parametrize("n,dl,nchan,T,ks", [(256, 0.5, 2, 3, 8), (192, 0.5, 1, 4, 8), (112, 0.75, 2, 5, 2),
+                                              (80, 1.0, 2, 5, 1)])
+def test_wide_grids(E, n, dl, nchan, T, ks):
     """256 x 256 and 192 x 192 grids (image columns over eight workgroups per
-    spectrum) against the oracle, station layout at half-wavelength spacing."""
+    spectrum), 112 x 112 (two) and 80 x 80 (one) against the oracle, station
+    layout at half- to one-wavelength spacing."""
     import dataclasses
     sub = dataclasses.replace(synth.shrink(synth.workload(2).subs[0], n_chan=nchan), grid_n=n, grid_dl=dl)
     x = synth.samples(sub, T)
     (gpu,), info = run_library(E, [sub], [x])
-    assert info["col_split"][0] == 8
+    assert info["col_split"][0] == ks
     fro, mx = assert_parity(gpu, oracle.image(sub, x), TOL, f"N={n}")
     print(f"N={n}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
