@@ -165,12 +165,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     float2 tw[8];
 #pragma unroll
     for (int n1 = 0; n1 < 8; ++n1) tw[n1] = a.twiddle[(n1 * q) % N];
-    // row-pass lanes (qr, kr): this part's q values, N row slots each (with
-    // KS = 1 these are the column lanes (q, kk) again)
     constexpr int QS = Sh::QS;
-    int qr = lane_on ? kpart * QS + tid / N : 0;
-    if constexpr (N % 64 == 0) qr = __builtin_amdgcn_readfirstlane(qr);
-    const int kr = lane_on ? tid % N : 0;
     // image column of local column kk
     auto column_of = [&](int k) {
         if constexpr (KS == 1) return k;
@@ -231,6 +226,8 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         const int slot = slot_of(ps.gp, v, t, T, 0, 1, L);
         const ChanInfo ci = a.chans[c];
         const int R = ci.R, W = ci.W, n_cell = ci.n_cell;
+        const int PR = P * R;
+        const float inv_pr = 1.0f / (float)PR;
         const CellDesc* g_desc = a.cells_desc + ci.cell_off;
         const uint2* g_gant = a.grp_ant + ci.grp_off;
         const float4* g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
@@ -289,20 +286,27 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             }
             __syncthreads();
 
-            // 3a. row pass: R rows per pol, this part's q values; local
-            //     column qr - kpart QS + QS m holds image column qr + Q m
-            if (lane_on) {
-                for (int rr = kr; rr < P * R; rr += N) {
-                    const int p = (P == 2 && rr >= R) ? 1 : 0;
-                    const int r = rr - p * R;
-                    float2 z[8];
-                    // with KS = 1, qr = q and tw holds its factors
-                    fold_twiddle<N, (KS > 1)>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, s_tw, qr);
-                    fft8(z);
-                    float2* yrow = s_Y + (p * a.Rmax + r) * a.YP + (qr - kpart * QS);
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) yrow[QS * m] = z[fft8_pos(m)];
+            // 3a. row pass: the P R window rows x this part's QS values of q,
+            //     packed densely onto the lanes (task tau = qi P R + row);
+            //     local column qi + QS m holds image column qr + Q m
+            for (int tau = tid; tau < PR * QS; tau += THREADS) {
+                // tau / PR through the segment's reciprocal: tau < 2^14 and
+                // PR <= 512, so the product is never high and at most one low
+                int qi = (int)((float)tau * inv_pr);
+                int rr = tau - qi * PR;
+                if (rr >= PR) {
+                    ++qi;
+                    rr -= PR;
                 }
+                const int qr = kpart * QS + qi;
+                const int p = (P == 2 && rr >= R) ? 1 : 0;
+                const int r = rr - p * R;
+                float2 z[8];
+                fold_twiddle<N, true>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, s_tw, qr);
+                fft8(z);
+                float2* yrow = s_Y + (p * a.Rmax + r) * a.YP + qi;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) yrow[QS * m] = z[fft8_pos(m)];
             }
             __syncthreads();
 
