@@ -52,7 +52,7 @@ struct Fp32Args {
     const float2* twiddle;    // [N]
     float* slots;             // [S][C][NPP][N][N]
     float2* efield;           // E-field form: [T][C][P][N][N] output images
-    int Rmax, WP, YP;
+    int Rmax, WP;             // window rows (padded), gather-program row pitch
     uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
     int nibble_order;
     int dbuf;                 // 1: two sample buffers (decode overlaps gridding)
@@ -80,18 +80,18 @@ struct Shape {
 constexpr int kPrefetch = 1;   // sample words per thread held in registers ahead of use (more are loaded directly)
 
 // ---- DFT input fold ---------------------------------------------------------
-// z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * stride] * w_Q^{n2 q} over
+// z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * STRIDE] * w_Q^{n2 q} over
 // the len non-zero inputs, nb = ceil(len / 8).  The window is zero-padded to
 // whole blocks of 8, so the first block is a plain load and no block needs a
 // bounds check; when the last block's non-zero part fits in its first half,
 // only that half is folded.  Control flow depends only on len (uniform).
 // s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}, or with
 // TW_LDS the factors are read from s_tw (n1 q < 7 Q < N) and tw is unused.
-template <int N, bool TW_LDS = false>
-__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int stride, int len,
+template <int N, bool TW_LDS, int STRIDE>
+__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int len,
                                              const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = v[k * stride];
+    for (int k = 0; k < 8; ++k) z[k] = v[k * STRIDE];
     const int nb = (len + 7) >> 3;
     int widx = 0;   // (8 n2 q) mod N
     // not unrolled: an unrolled loop lets the compiler hoist every block's LDS
@@ -101,20 +101,20 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
         widx += 8 * q;
         if (widx >= N) widx -= N;
         const float2 w = s_tw[widx];
-        const float2* vb = v + 8 * n2 * stride;
+        const float2* vb = v + 8 * n2 * STRIDE;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+        for (int k = 0; k < 8; ++k) z[k] = cfma(z[k], vb[k * STRIDE], w);
     }
     if (nb >= 2) {
         widx += 8 * q;
         if (widx >= N) widx -= N;
         const float2 w = s_tw[widx];
-        const float2* vb = v + 8 * (nb - 1) * stride;
+        const float2* vb = v + 8 * (nb - 1) * STRIDE;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+        for (int k = 0; k < 4; ++k) z[k] = cfma(z[k], vb[k * STRIDE], w);
         if (len - 8 * (nb - 1) > 4) {
 #pragma unroll
-            for (int k = 4; k < 8; ++k) z[k] = cfma(z[k], vb[k * stride], w);
+            for (int k = 4; k < 8; ++k) z[k] = cfma(z[k], vb[k * STRIDE], w);
         }
     }
 #pragma unroll
@@ -166,6 +166,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 #pragma unroll
     for (int n1 = 0; n1 < 8; ++n1) tw[n1] = a.twiddle[(n1 * q) % N];
     constexpr int QS = Sh::QS;
+    constexpr int YP = NK + 1;   // s_Y row pitch (float2), as laid out on the host
     // image column of local column kk
     auto column_of = [&](int k) {
         if constexpr (KS == 1) return k;
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         // zero the window buffers: cells beyond W (and rows beyond R) up to
         // the next multiple of 8 are read by the folds and must be zero
         for (int k = tid; k < P * a.Rmax * a.WP; k += THREADS) s_G[k] = make_float2(0.f, 0.f);
-        for (int k = tid; k < P * a.Rmax * a.YP; k += THREADS) s_Y[k] = make_float2(0.f, 0.f);
+        for (int k = tid; k < P * a.Rmax * YP; k += THREADS) s_Y[k] = make_float2(0.f, 0.f);
         float acc[8][NPP];
 #pragma unroll
         for (int m = 0; m < 8; ++m)
@@ -302,9 +303,9 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 const int p = (P == 2 && rr >= R) ? 1 : 0;
                 const int r = rr - p * R;
                 float2 z[8];
-                fold_twiddle<N, true>(z, s_G + (p * a.Rmax + r) * a.WP, 1, W, tw, s_tw, qr);
+                fold_twiddle<N, true, 1>(z, s_G + (p * a.Rmax + r) * a.WP, W, tw, s_tw, qr);
                 fft8(z);
-                float2* yrow = s_Y + (p * a.Rmax + r) * a.YP + qi;
+                float2* yrow = s_Y + (p * a.Rmax + r) * YP + qi;
 #pragma unroll
                 for (int m = 0; m < 8; ++m) yrow[QS * m] = z[fft8_pos(m)];
             }
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         float2 X[8];
-                        fold_twiddle<N>(X, s_Y + p * a.Rmax * a.YP + kk, a.YP, R, tw, s_tw, q);
+                        fold_twiddle<N, false, YP>(X, s_Y + p * a.Rmax * YP + kk, R, tw, s_tw, q);
                         fft8(X);
                         float2* out = a.efield + ((tt * a.C + c) * P + p) * (int64_t)N * N;
 #pragma unroll
@@ -349,11 +350,11 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             // 3b + 4. column pass per pol, products and accumulation in registers
             if (!EF && lane_on) {
                 float2 X[8];
-                fold_twiddle<N>(X, s_Y + kk, a.YP, R, tw, s_tw, q);
+                fold_twiddle<N, false, YP>(X, s_Y + kk, R, tw, s_tw, q);
                 fft8(X);
                 if constexpr (P == 2) {
                     float2 Yv[8];
-                    fold_twiddle<N>(Yv, s_Y + a.Rmax * a.YP + kk, a.YP, R, tw, s_tw, q);
+                    fold_twiddle<N, false, YP>(Yv, s_Y + a.Rmax * YP + kk, R, tw, s_tw, q);
                     fft8(Yv);
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
@@ -535,7 +536,7 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.grp_w = reinterpret_cast<const float4*>(d.grp_w);
     a.twiddle = d.twiddle; a.slots = d.slots;
     a.efield = reinterpret_cast<float2*>(efield);
-    a.Rmax = d.Rmax; a.WP = d.WP; a.YP = L.YP;
+    a.Rmax = d.Rmax; a.WP = d.WP;
     a.off_w = L.off_w; a.off_gant = L.off_gant; a.off_desc = L.off_desc;
     a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw;
     a.nibble_order = d.nibble_order;
