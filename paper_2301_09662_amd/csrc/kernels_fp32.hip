@@ -87,12 +87,55 @@ constexpr int kPrefetch = 1;   // sample words per thread held in registers ahea
 // only that half is folded.  Control flow depends only on len (uniform).
 // s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}, or with
 // TW_LDS the factors are read from s_tw (n1 q < 7 Q < N) and tw is unused.
-template <int N, bool TW_LDS, int STRIDE>
-__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int len,
-                                             const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
+//
+// Windows of two or three blocks (the common case) take fold_fixed, which
+// issues every LDS load of the fold before its first product, so a lane
+// waits for LDS once per fold rather than once per block.
+template <int N, bool TW_LDS, int STRIDE, int NB, bool HALF>
+__device__ __forceinline__ void fold_fixed(float2 (&z)[8], const float2* __restrict__ v, const float2 (&tw)[8],
+                                           const float2* __restrict__ s_tw, int q) {
+    constexpr int LAST = HALF ? 4 : 8;   // inputs folded from the last block
+    float2 b[NB - 1][8], w[NB - 1], t[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = v[k * STRIDE];
+    int widx = 0;   // (8 n2 q) mod N
+#pragma unroll
+    for (int n2 = 1; n2 < NB; ++n2) {
+        widx += 8 * q;
+        if (widx >= N) widx -= N;
+        w[n2 - 1] = s_tw[widx];
+#pragma unroll
+        for (int k = 0; k < ((n2 == NB - 1) ? LAST : 8); ++k) b[n2 - 1][k] = v[(8 * n2 + k) * STRIDE];
+    }
+    if constexpr (TW_LDS) {
+#pragma unroll
+        for (int n1 = 1; n1 < 8; ++n1) t[n1] = s_tw[n1 * q];
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < NB; ++n2)
+#pragma unroll
+        for (int k = 0; k < ((n2 == NB - 1) ? LAST : 8); ++k) z[k] = cfma(z[k], b[n2 - 1][k], w[n2 - 1]);
+#pragma unroll
+    for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], TW_LDS ? t[n1] : tw[n1]);   // w^0 = 1
+}
+
+template <int N, bool TW_LDS, int STRIDE, bool FIXED>
+__device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int len,
+                                             const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
     const int nb = (len + 7) >> 3;
+    const bool half = len - 8 * (nb - 1) <= 4;
+    if (FIXED && nb == 3) {
+        if (half) fold_fixed<N, TW_LDS, STRIDE, 3, true>(z, v, tw, s_tw, q);
+        else fold_fixed<N, TW_LDS, STRIDE, 3, false>(z, v, tw, s_tw, q);
+        return;
+    }
+    if (FIXED && nb == 2) {
+        if (half) fold_fixed<N, TW_LDS, STRIDE, 2, true>(z, v, tw, s_tw, q);
+        else fold_fixed<N, TW_LDS, STRIDE, 2, false>(z, v, tw, s_tw, q);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = v[k * STRIDE];
     int widx = 0;   // (8 n2 q) mod N
     // not unrolled: an unrolled loop lets the compiler hoist every block's LDS
     // loads above the exit test, which costs ~100 registers
@@ -167,6 +210,10 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     for (int n1 = 0; n1 < 8; ++n1) tw[n1] = a.twiddle[(n1 * q) % N];
     constexpr int QS = Sh::QS;
     constexpr int YP = NK + 1;   // s_Y row pitch (float2), as laid out on the host
+    // grids up to 64: windows of at most a few blocks, folded with every load
+    // issued up front (rows), and the column lanes' twiddles read from LDS
+    // (q is wave-uniform there) to leave the registers to those loads
+    constexpr bool kSmallGrid = N <= 64;
     // image column of local column kk
     auto column_of = [&](int k) {
         if constexpr (KS == 1) return k;
@@ -303,7 +350,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 const int p = (P == 2 && rr >= R) ? 1 : 0;
                 const int r = rr - p * R;
                 float2 z[8];
-                fold_twiddle<N, true, 1>(z, s_G + (p * a.Rmax + r) * a.WP, W, tw, s_tw, qr);
+                fold_twiddle<N, true, 1, kSmallGrid>(z, s_G + (p * a.Rmax + r) * a.WP, W, tw, s_tw, qr);
                 fft8(z);
                 float2* yrow = s_Y + (p * a.Rmax + r) * YP + qi;
 #pragma unroll
@@ -333,7 +380,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         float2 X[8];
-                        fold_twiddle<N, false, YP>(X, s_Y + p * a.Rmax * YP + kk, R, tw, s_tw, q);
+                        fold_twiddle<N, kSmallGrid, YP, false>(X, s_Y + p * a.Rmax * YP + kk, R, tw, s_tw, q);
                         fft8(X);
                         float2* out = a.efield + ((tt * a.C + c) * P + p) * (int64_t)N * N;
 #pragma unroll
@@ -350,11 +397,11 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             // 3b + 4. column pass per pol, products and accumulation in registers
             if (!EF && lane_on) {
                 float2 X[8];
-                fold_twiddle<N, false, YP>(X, s_Y + kk, R, tw, s_tw, q);
+                fold_twiddle<N, kSmallGrid, YP, false>(X, s_Y + kk, R, tw, s_tw, q);
                 fft8(X);
                 if constexpr (P == 2) {
                     float2 Yv[8];
-                    fold_twiddle<N, false, YP>(Yv, s_Y + a.Rmax * YP + kk, R, tw, s_tw, q);
+                    fold_twiddle<N, kSmallGrid, YP, false>(Yv, s_Y + a.Rmax * YP + kk, R, tw, s_tw, q);
                     fft8(Yv);
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
