@@ -62,3 +62,31 @@ def assert_parity(gpu, ora, tol, what=""):
     assert fro.max() <= tol, f"{what}: max per-image relative error {fro.max():.3e} > {tol:.1e}"
     assert mx.max() <= tol, f"{what}: max |diff| / peak {mx.max():.3e} > {tol:.1e}"
     return fro.max(), mx.max()
+
+
+_ORACLE_CACHE: dict = {}
+
+
+def oracle_channels(cfg: int, T: int, chans) -> tuple:
+    """Samples of workload ``cfg`` (T spectra, seeded) and the oracle's image
+    cube restricted to ``chans``, cached per process so that the FP32 and FP16
+    full-size tests share one oracle run."""
+    import synth
+    key = (cfg, T, tuple(chans))
+    if key not in _ORACLE_CACHE:
+        sub = synth.workload(cfg).subs[0]
+        x = synth.samples(sub, T)
+        ora = np.zeros((sub.n_chan, 4 if sub.n_pol == 2 else 1, sub.grid_n, sub.grid_n))
+        for c in chans:
+            ora[c] = oracle.image(sub, x, chans=range(c, c + 1))[c]
+        _ORACLE_CACHE.clear()   # one full-size workload held at a time
+        _ORACLE_CACHE[key] = (sub, x, ora)
+    return _ORACLE_CACHE[key]
+
+
+def check_invariants(gpu: np.ndarray):
+    """Properties every dual-pol image cube has: finite, XX and YY >= 0, and
+    |XY*|^2 <= XX * YY per pixel (Cauchy-Schwarz), up to FP32 rounding."""
+    assert np.isfinite(gpu).all()
+    assert (gpu[:, 0] >= 0).all() and (gpu[:, 1] >= 0).all()
+    assert (gpu[:, 2] ** 2 + gpu[:, 3] ** 2 <= gpu[:, 0] * gpu[:, 1] * (1 + 1e-4) + 1e-3).all()

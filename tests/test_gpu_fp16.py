@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import assert_parity, image_errors, run_library
+from gpu_util import assert_parity, check_invariants, image_errors, oracle_channels, run_library
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-3
@@ -88,3 +88,15 @@ def test_degenerate_arrays_and_swapped_nibbles(E):
         for order in (0, 1):
             (gpu,), _ = run_library(E, [s], [x], precision="fp16", nibble_order=order)
             assert_parity(gpu, oracle.image(s, x, nibble_order=order), TOL, f"fp16 edge{len(xy)} order{order}")
+
+
+def test_full_large_array_sampled_channels(E):
+    """The 2048-antenna array at full size (256 channels, N = 128, 125 spectra
+    in one call) in the FP16 form, against the oracle on three channels."""
+    chans = (0, 128, 255)
+    sub, x, ora = oracle_channels(5, 125, chans)
+    (gpu,), _ = run_library(E, [sub], [x], precision="fp16")
+    for c in chans:
+        fro, mx = assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"large array fp16 full, channel {c}")
+        print(f"large array fp16 channel {c}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+    check_invariants(gpu)

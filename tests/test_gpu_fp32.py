@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import assert_parity, run_library, torch_dev
+from gpu_util import assert_parity, check_invariants, oracle_channels, run_library, torch_dev
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -169,3 +169,27 @@ def test_wide_grids(E, n, dl, nchan, T, ks):
     assert info["col_split"][0] == ks
     fro, mx = assert_parity(gpu, oracle.image(sub, x), TOL, f"N={n}")
     print(f"N={n}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+
+
+def test_full_large_array_sampled_channels(E):
+    """2048 dual-pol antennas, 256 channels, N = 128, 125 spectra in one call
+    (the benchmark's launch shape, image columns over two workgroups),
+    against the oracle on three channels; invariants on all."""
+    chans = (0, 128, 255)
+    sub, x, ora = oracle_channels(5, 125, chans)
+    (gpu,), info = run_library(E, [sub], [x])
+    assert info["col_split"][0] == 2
+    for c in chans:
+        assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"large array full, channel {c}")
+    check_invariants(gpu)
+
+
+def test_full_wide_grid_sampled_channel(E):
+    """The station on a 256 x 256 grid at half-wavelength cells (132 channels,
+    100 spectra in one call; columns over eight workgroups) against the oracle
+    on its highest channel, where the window is largest."""
+    sub, x, ora = oracle_channels(6, 100, (131,))
+    (gpu,), info = run_library(E, [sub], [x])
+    assert info["col_split"][0] == 8
+    assert_parity(gpu[131:132], ora[131:132], TOL, "256 grid full, channel 131")
+    check_invariants(gpu)
