@@ -501,6 +501,9 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         epic_status s = geometry(h);
         if (s != EPIC_OK) return s;
         build_gather(h);
+        // the gather program stores a cell's window offset r * WP + w in 16
+        // bits; such windows (~255 x 255 cells) never fit LDS anyway
+        if ((int64_t)h.dev.Rmax * h.dev.WP > 65536) return EPIC_E_UNSUPPORTED;
         SubDev& d = h.dev;
         d.A = h.desc.n_ant; d.P = h.desc.n_pol; d.C = h.desc.n_chan; d.N = h.desc.grid_n;
         d.K = h.desc.kernel_k; d.NPP = (d.P == 2) ? 4 : 1; d.nibble_order = h.desc.nibble_order;

@@ -160,3 +160,19 @@ def test_arrays_too_large_for_lds_are_refused(E):
         with pytest.raises(E.EpicError) as ei:
             dry(E, [big], prec, 4)
         assert ei.value.status == E.EPIC_E_UNSUPPORTED
+
+
+def test_window_spanning_a_256_grid_is_refused(E):
+    """Antennas whose footprints span the whole 256 x 256 grid: the window
+    (and its 16-bit cell offsets) does not fit a workgroup, so the plan says
+    so rather than launching."""
+    import dataclasses
+    base = synth.shrink(synth.workload(2).subs[0], n_chan=1)
+    lam = 299792458.0 / base.freq0_hz
+    d = 126 * base.grid_dl * lam
+    xy = np.array([[-d, -d], [d, d], [-d, d], [d, -d]])
+    sub = dataclasses.replace(base, ant_xy=xy, grid_n=256)
+    for prec in ("fp32", "fp16"):
+        with pytest.raises(E.EpicError) as ei:
+            dry(E, [sub], prec, 4)
+        assert ei.value.status == E.EPIC_E_UNSUPPORTED
