@@ -75,6 +75,42 @@ def counter_traffic(precision, workload):
     return entry["bytes_per_launch"]
 
 
+MFMA_FLOPS = 2 * 16 * 16 * 32     # one v_mfma_f32_16x16x32_f16
+
+
+def mfma_ops_per_spectrum(plan, subs):
+    """MFMA 16x16x32 instructions the matrix-core kernel executes for one
+    spectrum of every channel of every sub-array, from the plan's shapes: per
+    column part, the row pass takes ceil(M1/16) x (2 NK/16) x KK products
+    (M1 = P x window rows rounded up to 4) and the column pass
+    (N/16) x (NK/16) x P x 2 x KK, with KK 32-deep steps covering the largest
+    window extent (rounded up to 8) and NK = N/KS columns per part."""
+    from paper_2301_09662_amd import epic as E
+    total = 0
+    for k, s in enumerate(subs):
+        g = E.epic_debug_geometry(plan, k)                     # [C][A][(x, y)] nearest cells
+        hk = s.kernel_k // 2
+        R = g[:, :, 1].max(1) - g[:, :, 1].min(1) + 1 + 2 * hk
+        W = g[:, :, 0].max(1) - g[:, :, 0].min(1) + 1 + 2 * hk
+        ext = max(-(-int(R.max()) // 8) * 8, -(-int(W.max()) // 8) * 8)
+        KK = -(-ext // 16)
+        N, P = s.grid_n, s.n_pol
+        KS = 2 if N > 64 else 1
+        NK = N // KS
+        M1 = P * ((R + 3) // 4 * 4)
+        per_c = KS * (-(-M1 // 16) * (2 * NK // 16) * KK + (N // 16) * (NK // 16) * P * 2 * KK)
+        total += int(per_c.sum())
+    return total
+
+
+def mfma_fraction(info, kern_ms):
+    """Executed FP16 MFMA rate of a matrix-core call against the dense peak."""
+    ops = info["mfma_ops_per_call"]
+    tflops = ops * MFMA_FLOPS / (kern_ms * 1e-3) / 1e12
+    return {"executed_ops_per_call": ops, "executed_tflops": tflops, "peak": FP16_MFMA_PEAK_TFLOPS,
+            "frac": tflops / FP16_MFMA_PEAK_TFLOPS, "source": "tile counts of the plan's shapes"}
+
+
 def rel_image_errors(img, ref):
     """Per-image relative Frobenius error [C][NPP] of img against ref; the
     cross products are normalised by sqrt(|XX| |YY|) of ref."""
@@ -176,6 +212,8 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        if precision == "fp16":
+            info = dict(info, mfma_ops_per_call=mfma_ops_per_spectrum(plan, subs) * T)
         E.epic_destroy(plan)
         return wall / steps * 1e3, kern_ms, [o.double().cpu().numpy() for o in outs], info
 
@@ -211,10 +249,12 @@ def main():
                      "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch,
                      "frac_of_nonpacked_issue": achieved / FP32_NONPACKED_TFLOPS},
     }
+    if res["roofline"]["traffic"] is not None:
+        res["roofline"]["hbm_frac"] = res["roofline"]["traffic"] / (kern_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
     if precision == "fp16":
-        # matrix-core form: MFMA peak for context; the kernel is issue bound
-        # on its vector work (gathering, FP16 packing, products)
-        res["roofline"].update({"bound": "alu", "peak_fp16_mfma_tflops": FP16_MFMA_PEAK_TFLOPS})
+        # matrix-core form: the kernel is issue bound on its vector work
+        # (gathering, FP16 packing, products); executed MFMA work for context
+        res["roofline"]["mfma"] = mfma_fraction(info32, kern_ms)
     red_form = not args.no_reduced and precision == "fp32"
     if red_form:
         try:
@@ -229,7 +269,8 @@ def main():
         red = {"precision": "fp16", "value": samples_per_step / (ms16 * 1e-3), "ms_per_step": ms16,
                "kernel_ms": kern16, "speedup_vs_fp32": ms_per_step / ms16,
                "max_rel_image_err_vs_fp32_all_channels": float(max(errs)),
-               "achieved_algorithmic_tflops": flops_per_launch / (kern16 * 1e-3) / 1e12}
+               "achieved_algorithmic_tflops": flops_per_launch / (kern16 * 1e-3) / 1e12,
+               "mfma": mfma_fraction(info16, kern16)}
         res["reduced_precision"] = red
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(subs[0], host[0])
