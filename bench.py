@@ -145,6 +145,62 @@ def cpu_baseline(sub, samples, budget_s=15.0):
                       f"({wall:.1f} s wall, FP64 C loops, OpenMP over channels)"}
 
 
+def numpy_fft_image(sub, x, c):
+    """One channel's image cube [NPP][N][N] computed the plain vectorised way
+    in FP32 NumPy/SciPy: nearest-cell Gaussian gridding as a sparse matrix
+    (taps times the (-1)^(x+y) centring), unnormalised exp(+2 pi i) 2D FFT,
+    products XX*, YY*, Re XY*, Im XY* summed over the spectra of x
+    (uint8 [T][A][P], nibble order 0).  CPU context for the benchmark, not an
+    oracle."""
+    import scipy.sparse as sp
+    N, K, P, A = sub.grid_n, sub.kernel_k, sub.n_pol, sub.n_ant
+    hk = K // 2
+    b = np.arange(256)
+    hi, lo = ((b >> 4) ^ 8) - 8, ((b & 15) ^ 8) - 8
+    lut = (hi + 1j * lo).astype(np.complex64)
+    lam = 299792458.0 / (sub.freq0_hz + c * sub.dfreq_hz)
+    g = sub.ant_xy / lam / sub.grid_dl + N / 2                       # [A][(x, y)] in cells
+    p0 = np.floor(g + 0.5).astype(np.int64)
+    d = np.arange(-hk, hk + 1)
+    cx = p0[:, 0, None, None] + d[None, None, :]                      # [A][dy][dx]
+    cy = p0[:, 1, None, None] + d[None, :, None]
+    w = np.exp(-((cx - g[:, 0, None, None]) ** 2 + (cy - g[:, 1, None, None]) ** 2) / (2 * 0.5 ** 2))
+    w /= w.sum(axis=(1, 2), keepdims=True)
+    w *= np.where((cx + cy) % 2 == 0, 1.0, -1.0)
+    M = sp.csr_matrix((w.ravel().astype(np.float32), ((cy * N + cx).ravel(), np.repeat(np.arange(A), K * K))),
+                      shape=(N * N, A))
+    T = x.shape[0]
+    E = lut[x]                                                        # [T][A][P]
+    G = (M @ E.transpose(1, 0, 2).reshape(A, T * P)).reshape(N, N, T, P)
+    F = np.fft.ifft2(G, axes=(0, 1)).astype(np.complex64) * np.float32(N * N)
+    X = F[..., 0]
+    out = [np.sum(np.abs(X) ** 2, axis=2)]
+    if P == 2:
+        Y = F[..., 1]
+        xy = np.sum(X * np.conj(Y), axis=2)
+        out += [np.sum(np.abs(Y) ** 2, axis=2), xy.real, xy.imag]
+    return np.stack(out)
+
+
+def cpu_numpy_fft(sub, samples, budget_s=10.0):
+    """Time numpy_fft_image on the first channels of the workload (all
+    spectra), as many as fit ~budget_s; NumPy's FFT and SciPy's sparse
+    product run on one thread."""
+    C = sub.n_chan
+    t0 = time.perf_counter()
+    numpy_fft_image(sub, samples[:, 0], 0)
+    dt = time.perf_counter() - t0
+    n_c = int(max(1, min(C, budget_s / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    for c in range(n_c):
+        numpy_fft_image(sub, samples[:, c], c)
+    wall = time.perf_counter() - t0
+    n = sub.n_ant * sub.n_pol * n_c * samples.shape[0]
+    return {"value": n / wall, "unit": "samples/s", "cores": 1, "kind": "numpy-fft (context, not an oracle)",
+            "sample": f"first {n_c} of {C} channels x all {samples.shape[0]} spectra ({wall:.1f} s wall, "
+                      f"FP32 sparse gridding + FFT)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +330,7 @@ def main():
         res["reduced_precision"] = red
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(subs[0], host[0])
+        res["cpu_numpy_fft"] = cpu_numpy_fft(subs[0], host[0])
     print(json.dumps(res), flush=True)
 
 
