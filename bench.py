@@ -187,6 +187,7 @@ def cpu_numpy_fft(sub, samples, budget_s=10.0):
     spectra), as many as fit ~budget_s; NumPy's FFT and SciPy's sparse
     product run on one thread."""
     C = sub.n_chan
+    numpy_fft_image(sub, samples[:2, 0], 0)   # imports and first-call set-up, untimed
     t0 = time.perf_counter()
     numpy_fft_image(sub, samples[:, 0], 0)
     dt = time.perf_counter() - t0
