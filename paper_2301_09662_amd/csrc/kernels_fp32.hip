@@ -222,6 +222,9 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 
     const int AP = a.A * P;
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.samples) & 3) == 0);
+    // decoding runs on the workgroup's last lanes: the gather cells are sorted
+    // by group count, so the first waves carry the longest gather chains
+    const int dtid = THREADS - 1 - tid;
     const int nwords = AP >> 2;
 
     uint32_t pre[kPrefetch];   // the next spectrum's sample words, loaded ahead of use
@@ -230,7 +233,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + vv) * AP);
 #pragma unroll
         for (int k = 0; k < kPrefetch; ++k) {
-            const int w = tid + k * THREADS;
+            const int w = dtid + k * THREADS;
             pre[k] = (w < nwords) ? row4[w] : 0u;
         }
     };
@@ -241,7 +244,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         if (words) {
 #pragma unroll
             for (int k = 0; k < kPrefetch; ++k) {
-                const int w = tid + k * THREADS;
+                const int w = dtid + k * THREADS;
                 if (w < nwords) {
                     const uint32_t x = pre[k];
                     dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
@@ -251,7 +254,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 }
             }
             const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
-            for (int w = tid + kPrefetch * THREADS; w < nwords; w += THREADS) {
+            for (int w = dtid + kPrefetch * THREADS; w < nwords; w += THREADS) {
                 const uint32_t x = row4[w];
                 dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
                 dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             }
         } else {
             const uint8_t* row = a.samples + ((int64_t)tt * a.C + cc) * AP;
-            for (int k = tid; k < AP; k += THREADS) dst[k] = unpack44(row[k], a.nibble_order);
+            for (int k = dtid; k < AP; k += THREADS) dst[k] = unpack44(row[k], a.nibble_order);
         }
     };
 
