@@ -127,6 +127,22 @@ def _dev_ptr(t) -> int:
     return t.data_ptr()
 
 
+def _check_buffer(t, dtype: str, count: int, what: str):
+    """A tensor argument must hold at least ``count`` elements of ``dtype``
+    (raw device addresses are taken as they are: their size is the caller's
+    responsibility, as in the C ABI)."""
+    if isinstance(t, int):
+        return
+    if str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{what}: {dtype} tensor expected, got {t.dtype}")
+    if t.numel() < count:
+        raise ValueError(f"{what}: {count} elements needed, tensor has {t.numel()}")
+
+
+def _npp(plan, s) -> int:
+    return 4 if int(s.n_pol) == 2 else 1
+
+
 class Plan:
     """Owns an ``epic_plan_t`` handle and the host copies kept alive for it."""
 
@@ -197,6 +213,11 @@ def epic_plan(subs: Sequence, precision=EPIC_FP32, gridder=EPIC_GRID_AUTO, outpu
 def epic_grid_fft_accumulate(plan: Plan, samples: Sequence, n_time: int, stream=None):
     """Enqueue the hot path on ``stream``; ``samples[s]`` is a uint8 device
     tensor [n_time][C][A][P] (or a raw device address)."""
+    if len(samples) != len(plan.subs):
+        raise ValueError(f"one sample buffer per sub-array expected ({len(plan.subs)}), got {len(samples)}")
+    for k, (t, s) in enumerate(zip(samples, plan.subs)):
+        _check_buffer(t, "uint8", int(n_time) * int(s.n_chan) * int(np.asarray(s.ant_xy).shape[0]) * int(s.n_pol),
+                      f"samples[{k}]")
     ptrs = (_vp * max(len(samples), 1))(*[_dev_ptr(t) for t in samples])
     _check(_lib.epic_grid_fft_accumulate(plan, ptrs, int(n_time), _stream_handle(stream)),
            "epic_grid_fft_accumulate")
@@ -205,12 +226,23 @@ def epic_grid_fft_accumulate(plan: Plan, samples: Sequence, n_time: int, stream=
 def epic_readout(plan: Plan, images: Sequence, reset: int = 0, stream=None):
     """Reduce the accumulators into ``images[s]`` (float32 device tensors
     [C][NPP][N][N]); zero them afterwards if ``reset``."""
+    if len(images) != len(plan.subs):
+        raise ValueError(f"one image cube per sub-array expected ({len(plan.subs)}), got {len(images)}")
+    for k, (t, s) in enumerate(zip(images, plan.subs)):
+        _check_buffer(t, "float32", int(s.n_chan) * _npp(plan, s) * int(s.grid_n) ** 2, f"images[{k}]")
     ptrs = (_vp * max(len(images), 1))(*[_dev_ptr(t) for t in images])
     _check(_lib.epic_readout(plan, ptrs, int(reset), _stream_handle(stream)), "epic_readout")
 
 
 def epic_set_gains(plan: Plan, sub: int, gains: Optional[np.ndarray], stream=None):
+    """Per-antenna complex gains of sub-array ``sub``: host float32
+    [C][A][P][2] (re, im), or None for unit gains."""
     g = None if gains is None else np.ascontiguousarray(np.asarray(gains, dtype=np.float32))
+    if g is not None and 0 <= int(sub) < len(plan.subs):
+        s = plan.subs[int(sub)]
+        n = int(s.n_chan) * int(np.asarray(s.ant_xy).shape[0]) * int(s.n_pol) * 2
+        if g.size != n:
+            raise ValueError(f"gains: {n} floats ([C][A][P][2]) expected, got {g.size}")
     ptr = _P(ctypes.c_float)() if g is None else g.ctypes.data_as(_P(ctypes.c_float))
     _check(_lib.epic_set_gains(plan, int(sub), ptr, _stream_handle(stream)), "epic_set_gains")
 
@@ -218,6 +250,11 @@ def epic_set_gains(plan: Plan, sub: int, gains: Optional[np.ndarray], stream=Non
 def epic_efield(plan: Plan, sub: int, samples, n_time: int, out, stream=None):
     """E-field images of sub-array ``sub``: ``out`` is a float32 device tensor
     [n_time][C][P][N][N][2] (or a raw device address)."""
+    if 0 <= int(sub) < len(plan.subs):
+        s = plan.subs[int(sub)]
+        A = int(np.asarray(s.ant_xy).shape[0])
+        _check_buffer(samples, "uint8", int(n_time) * int(s.n_chan) * A * int(s.n_pol), "samples")
+        _check_buffer(out, "float32", int(n_time) * int(s.n_chan) * int(s.n_pol) * int(s.grid_n) ** 2 * 2, "out")
     _check(_lib.epic_efield(plan, int(sub), _dev_ptr(samples), int(n_time), _dev_ptr(out), _stream_handle(stream)),
            "epic_efield")
 

@@ -162,3 +162,46 @@ def test_debug_calls_validate(E):
     with pytest.raises(E.EpicError) as e:
         E.epic_debug_unpack(1 << 20, -1, 0, 1 << 20, stream=0)
     assert e.value.status == E.EPIC_E_ARG
+
+
+class _FakeTensor:
+    """Stands in for a device tensor: the binding checks dtype and size
+    before any pointer reaches the library."""
+
+    def __init__(self, dtype, n):
+        self.dtype, self._n, self.is_cuda = dtype, n, True
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return True
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_binding_checks_buffers_before_the_library(E):
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=16)
+    plan = E.epic_plan([sub], max_time=4, flags=E.EPIC_F_DRY_RUN)
+    try:
+        need = 4 * 2 * 16 * 2
+        for bad, msg in ((_FakeTensor("torch.uint8", need - 1), "elements needed"),
+                         (_FakeTensor("torch.float32", need), "uint8 tensor expected")):
+            with pytest.raises(ValueError, match=msg):
+                E.epic_grid_fft_accumulate(plan, [bad], 4, stream=0)
+        with pytest.raises(ValueError, match="one sample buffer per sub-array"):
+            E.epic_grid_fft_accumulate(plan, [], 4, stream=0)
+        with pytest.raises(ValueError, match="elements needed"):
+            E.epic_readout(plan, [_FakeTensor("torch.float32", 2 * 4 * 64 * 64 - 1)], 1, stream=0)
+        with pytest.raises(ValueError, match="float32 tensor expected"):
+            E.epic_efield(plan, 0, _FakeTensor("torch.uint8", need), 4,
+                          _FakeTensor("torch.float16", 4 * 2 * 2 * 64 * 64 * 2), stream=0)
+        with pytest.raises(ValueError, match="gains"):
+            E.epic_set_gains(plan, 0, np.ones((2, 16, 2, 1), dtype=np.float32), stream=0)
+        # right sizes reach the library, which refuses a dry-run plan
+        with pytest.raises(E.EpicError) as ei:
+            E.epic_grid_fft_accumulate(plan, [_FakeTensor("torch.uint8", need)], 4, stream=0)
+        assert ei.value.status == E.EPIC_E_STATE
+    finally:
+        E.epic_destroy(plan)
