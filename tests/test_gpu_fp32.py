@@ -89,8 +89,9 @@ def test_reset_and_empty_calls(E):
         E.epic_readout(plan, [out], 1)                    # after reset: zero
         torch.cuda.synchronize()
         assert float(out.abs().max()) == 0.0
+        x9 = torch.from_numpy(synth.samples(sub, 9)).to(dev)
         with pytest.raises(E.EpicError) as e:
-            E.epic_grid_fft_accumulate(plan, [x], 9)      # beyond max_time
+            E.epic_grid_fft_accumulate(plan, [x9], 9)     # beyond max_time
         assert e.value.status == E.EPIC_E_ARG
     finally:
         E.epic_destroy(plan)
