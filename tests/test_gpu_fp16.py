@@ -100,3 +100,15 @@ def test_full_large_array_sampled_channels(E):
         fro, mx = assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"large array fp16 full, channel {c}")
         print(f"large array fp16 channel {c}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
     check_invariants(gpu)
+
+
+def test_single_pol_split_columns(E):
+    """Single-pol array on a 128 grid (columns over two workgroups) in the
+    FP16 form."""
+    import dataclasses
+    base = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    sub = dataclasses.replace(base, n_pol=1, grid_n=128, grid_dl=1.0)
+    x = synth.samples(sub, 5)
+    (gpu,), info = run_library(E, [sub], [x], precision="fp16")
+    assert info["col_split"][0] == 2 and info["npp"][0] == 1
+    assert_parity(gpu, oracle.image(sub, x), TOL, "fp16 single pol N=128")

@@ -194,3 +194,16 @@ def test_full_wide_grid_sampled_channel(E):
     assert info["col_split"][0] == 8
     assert_parity(gpu[131:132], ora[131:132], TOL, "256 grid full, channel 131")
     check_invariants(gpu)
+
+
+@pytest.mark.parametrize("n,dl,ks", [(128, 1.0, 2), (256, 0.5, 8)])
+def test_single_pol_split_columns(E, n, dl, ks):
+    """Single-pol arrays on grids whose columns span two or eight workgroups
+    (the row pass then holds one pol's rows only)."""
+    import dataclasses
+    base = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    sub = dataclasses.replace(base, n_pol=1, grid_n=n, grid_dl=dl)
+    x = synth.samples(sub, 5)
+    (gpu,), info = run_library(E, [sub], [x])
+    assert info["col_split"][0] == ks and info["npp"][0] == 1
+    assert_parity(gpu, oracle.image(sub, x), TOL, f"single pol N={n}")
