@@ -51,15 +51,17 @@ typedef enum {
 typedef enum {
     EPIC_FP32 = 0,   /* FP32 vector ALU: gather gridding + register FFT */
     EPIC_FP16 = 1,   /* FP16 matrix cores (MFMA) for the transform stages */
-    EPIC_FP8 = 2     /* FP8 e4m3 matrix cores for gridding, FP16 transforms */
+    EPIC_FP8 = 2     /* FP8 e4m3 matrix cores for gridding, FP16 transforms.
+                        Not built: epic_plan returns EPIC_E_UNSUPPORTED */
 } epic_precision;
 
 /* How the gridding step (Eq. 4, W_a * E_a summed over antennas) runs. */
 typedef enum {
-    EPIC_GRID_AUTO = 0,        /* library / autotuner choice */
+    EPIC_GRID_AUTO = 0,        /* library choice (the gather) */
     EPIC_GRID_GATHER = 1,      /* each aperture cell sums its antenna list (FP32 ALU) */
-    EPIC_GRID_DENSE_GEMM = 2,  /* kernel matrix x E-field GEMM on matrix cores */
-    EPIC_GRID_BLOCK_GEMM = 3   /* reserved: block-sparse GEMM */
+    EPIC_GRID_DENSE_GEMM = 2,  /* kernel matrix x E-field GEMM on matrix cores (not built:
+                                  EPIC_E_UNSUPPORTED) */
+    EPIC_GRID_BLOCK_GEMM = 3   /* block-sparse GEMM (not built: EPIC_E_UNSUPPORTED) */
 } epic_gridder;
 
 /* Output products per pixel. */
