@@ -205,3 +205,30 @@ def test_binding_checks_buffers_before_the_library(E):
         assert ei.value.status == E.EPIC_E_STATE
     finally:
         E.epic_destroy(plan)
+
+
+def test_plans_from_several_threads(E):
+    """Separate plans may be created, queried and destroyed from different
+    host threads at once (the library keeps its table of live plans under a
+    lock)."""
+    import threading
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2, n_ant=32)
+    errors, done = [], []
+
+    def work():
+        try:
+            for _ in range(15):
+                plan = E.epic_plan([sub], max_time=4, flags=E.EPIC_F_DRY_RUN)
+                assert E.epic_plan_query(plan)["n_sub"] == 1
+                E.epic_destroy(plan)
+                done.append(1)
+        except Exception as exc:   # reported by the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=work) for _ in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors[0]
+    assert len(done) == 8 * 15
