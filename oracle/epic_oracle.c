@@ -31,6 +31,30 @@
  *   - the fourth product printed in Sec. 3.2 is the conjugate of XY*, so the
  *     stored products are XX*, YY*, Re XY*, Im XY* (single pol: XX* only);
  *   - a footprint cell outside [0, N-1] is an error (no wrap, no clip).
+ *
+ * Pins (tests/test_oracle.py; each checks the function against something
+ * other than itself, and the planted-mistake tests show that a dropped term,
+ * a wrong sign, a transposed operand, a swapped conjugate or nibble, a lost
+ * checkerboard or normalisation, or truncation instead of rounding, each
+ * fails at least one of them):
+ *   ora_unpack_table    every byte against the two's-complement table, both
+ *                       nibble orders;
+ *   ora_geometry        closed-form positions (centre, whole cells, ties),
+ *                       scaling with frequency, out-of-grid refusal;
+ *   ora_taps            the Gaussian's closed form, its shift with the
+ *                       sub-cell offset, user taps passed through;
+ *   ora_dft2            numpy's inverse FFT times N^2, and the orientation of
+ *                       a single-cell grid's plane wave;
+ *   ora_grid, ora_image_range
+ *                       FX brute force (per-pair correlations imaged
+ *                       directly, Eq. 3 with Eq. 4), the worked example's
+ *                       closed form (tests/golden/worked_example.txt),
+ *                       Parseval, Y = i X conjugation order, invariants and
+ *                       linearity, point-source localisation;
+ *   ora_autocorr_range  FX imaging with the a = b terms dropped, and the sum
+ *                       of one-antenna images;
+ *   ora_efield_range    a lone antenna's field equals its kernel image, and
+ *                       the products of the fields sum to ora_image_range.
  */
 #include <math.h>
 #include <stdint.h>
