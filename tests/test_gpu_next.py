@@ -306,3 +306,19 @@ def test_two_plans_on_two_streams(E):
     finally:
         E.epic_destroy(pa)
         E.epic_destroy(pb)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp16", 1e-3)])
+def test_autocorr_removed_and_stokes_on_split_columns(E, precision, tol):
+    """Autocorrelation removal and the Stokes output on a 128 grid whose image
+    columns span two workgroups (512 antennas of the large array)."""
+    sub = synth.shrink(synth.workload(5).subs[0], n_chan=2, n_ant=512)
+    x = synth.samples(sub, 6)
+    (o,) = run_plan(E, [sub], [("acc", [x]), ("read", 1)], precision, flags=E.EPIC_F_REMOVE_AUTOCORR,
+                    output=E.EPIC_OUT_STOKES)
+    full = oracle.image(sub, x)
+    pol = full - oracle.autocorr(sub, x)
+    st = np.stack([pol[:, 0] + pol[:, 1], pol[:, 0] - pol[:, 1], 2 * pol[:, 2], -2 * pol[:, 3]], axis=1)
+    fst = np.stack([full[:, 0] + full[:, 1], full[:, 0] - full[:, 1], 2 * full[:, 2], -2 * full[:, 3]], axis=1)
+    peak = np.abs(fst[:, 0]).max()
+    assert np.abs(o[0] - st).max() <= tol * peak
