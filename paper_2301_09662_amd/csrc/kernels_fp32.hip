@@ -312,6 +312,11 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             float2* s_smp = (i & 1) ? s_smp1 : s_smp0;
             float2* s_nxt = (i & 1) ? s_smp0 : s_smp1;
 
+            // Wave priorities: the gathering and the row pass are chains of
+            // dependent LDS reads run by few waves, the column pass is VALU
+            // work on every wave; raising the first two lets a CU's other
+            // workgroup fill their gaps without delaying them.
+            __builtin_amdgcn_s_setprio(2);
             // 2. gather gridding of the non-empty cells, both pols per cell
             for (int k = tid; k < n_cell; k += THREADS) {
                 const uint2 d = PROG_LDS ? s_desc[k] : g_desc[k];
@@ -337,6 +342,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             }
             __syncthreads();
 
+            __builtin_amdgcn_s_setprio(1);
             // 3a. row pass: the P R window rows x this part's QS values of q,
             //     packed densely onto the lanes (task tau = qi P R + row);
             //     local column qi + QS m holds image column qr + Q m
@@ -397,6 +403,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                     }
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             // 3b + 4. column pass per pol, products and accumulation in registers
             if (!EF && lane_on) {
                 float2 X[8];

@@ -267,6 +267,9 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             float2* s_smp = (i & 1) ? s_smp1 : s_smp0;
             float2* s_nxt = (i & 1) ? s_smp0 : s_smp1;
 
+            // Wave priorities as in the FP32 kernel: the latency-bound gathering
+            // and row pass ahead of the column pass of a CU's other workgroups.
+            __builtin_amdgcn_s_setprio(2);
             // 2. gather gridding (FP32), stored as the FP16 row-pass operand:
             //    row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)]
             if (prog)
@@ -283,6 +286,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             }
             __syncthreads();
 
+            __builtin_amdgcn_s_setprio(1);
             // 3a. row pass: [M1 x K2] x [K2 x 2 NK] on the matrix cores; each wave
             //     takes NT1 output tiles and writes them, rounded to FP16, as the
             //     column-pass operand B2[p][i][Re Y(0..) | Im Y(0..)]
@@ -314,6 +318,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             }
             __syncthreads();
 
+            __builtin_amdgcn_s_setprio(0);
             // 3b + 4. column pass: E~ rows 16w.. for every own column tile, both
             //         pols, then the products of Eq. 5 accumulated in registers
             if (mwave) {
