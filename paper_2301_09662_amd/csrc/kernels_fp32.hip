@@ -83,18 +83,18 @@ constexpr int kPrefetch = 1;   // sample words per thread held in registers ahea
 // z[n1] = w_N^{n1 q} * sum_{n2 < nb} v[(n1 + 8 n2) * STRIDE] * w_Q^{n2 q} over
 // the len non-zero inputs, nb = ceil(len / 8).  The window is zero-padded to
 // whole blocks of 8, so the first block is a plain load and no block needs a
-// bounds check; when the last block's non-zero part fits in its first half,
-// only that half is folded.  Control flow depends only on len (uniform).
+// bounds check; of the last block only its first 1, 2, 4 or 8 inputs (the
+// non-zero part, rounded up) are folded.  Control flow depends only on len
+// (uniform).
 // s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}, or with
 // TW_LDS the factors are read from s_tw (n1 q < 7 Q < N) and tw is unused.
 //
 // Windows of two or three blocks (the common case) take fold_fixed, which
 // issues every LDS load of the fold before its first product, so a lane
 // waits for LDS once per fold rather than once per block.
-template <int N, bool TW_LDS, int STRIDE, int NB, bool HALF>
+template <int N, bool TW_LDS, int STRIDE, int NB, int LAST>
 __device__ __forceinline__ void fold_fixed(float2 (&z)[8], const float2* __restrict__ v, const float2 (&tw)[8],
                                            const float2* __restrict__ s_tw, int q) {
-    constexpr int LAST = HALF ? 4 : 8;   // inputs folded from the last block
     float2 b[NB - 1][8], w[NB - 1], t[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = v[k * STRIDE];
@@ -123,15 +123,19 @@ template <int N, bool TW_LDS, int STRIDE, bool FIXED>
 __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int len,
                                              const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
     const int nb = (len + 7) >> 3;
-    const bool half = len - 8 * (nb - 1) <= 4;
+    const int tail = len - 8 * (nb - 1);   // non-zero inputs of the last block, 1..8
     if (FIXED && nb == 3) {
-        if (half) fold_fixed<N, TW_LDS, STRIDE, 3, true>(z, v, tw, s_tw, q);
-        else fold_fixed<N, TW_LDS, STRIDE, 3, false>(z, v, tw, s_tw, q);
+        if (tail <= 1) fold_fixed<N, TW_LDS, STRIDE, 3, 1>(z, v, tw, s_tw, q);
+        else if (tail <= 2) fold_fixed<N, TW_LDS, STRIDE, 3, 2>(z, v, tw, s_tw, q);
+        else if (tail <= 4) fold_fixed<N, TW_LDS, STRIDE, 3, 4>(z, v, tw, s_tw, q);
+        else fold_fixed<N, TW_LDS, STRIDE, 3, 8>(z, v, tw, s_tw, q);
         return;
     }
     if (FIXED && nb == 2) {
-        if (half) fold_fixed<N, TW_LDS, STRIDE, 2, true>(z, v, tw, s_tw, q);
-        else fold_fixed<N, TW_LDS, STRIDE, 2, false>(z, v, tw, s_tw, q);
+        if (tail <= 1) fold_fixed<N, TW_LDS, STRIDE, 2, 1>(z, v, tw, s_tw, q);
+        else if (tail <= 2) fold_fixed<N, TW_LDS, STRIDE, 2, 2>(z, v, tw, s_tw, q);
+        else if (tail <= 4) fold_fixed<N, TW_LDS, STRIDE, 2, 4>(z, v, tw, s_tw, q);
+        else fold_fixed<N, TW_LDS, STRIDE, 2, 8>(z, v, tw, s_tw, q);
         return;
     }
 #pragma unroll
@@ -153,9 +157,13 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
         if (widx >= N) widx -= N;
         const float2 w = s_tw[widx];
         const float2* vb = v + 8 * (nb - 1) * STRIDE;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) z[k] = cfma(z[k], vb[k * STRIDE], w);
-        if (len - 8 * (nb - 1) > 4) {
+        z[0] = cfma(z[0], vb[0], w);
+        if (tail > 1) z[1] = cfma(z[1], vb[STRIDE], w);
+        if (tail > 2) {
+            z[2] = cfma(z[2], vb[2 * STRIDE], w);
+            z[3] = cfma(z[3], vb[3 * STRIDE], w);
+        }
+        if (tail > 4) {
 #pragma unroll
             for (int k = 4; k < 8; ++k) z[k] = cfma(z[k], vb[k * STRIDE], w);
         }
