@@ -287,6 +287,13 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
         const int R = ci.R, W = ci.W, n_cell = ci.n_cell;
         const int PR = P * R;
         const float inv_pr = 1.0f / (float)PR;
+        // the lane's first row-pass task (tau = tid) for the whole segment
+        int qi_0 = (int)((float)tid * inv_pr);
+        int rr_0 = tid - qi_0 * PR;
+        if (rr_0 >= PR) {
+            ++qi_0;
+            rr_0 -= PR;
+        }
         const CellDesc* g_desc = a.cells_desc + ci.cell_off;
         const uint2* g_gant = a.grp_ant + ci.grp_off;
         const float4* g_w = a.grp_w + (int64_t)ci.grp_off * GF4;
@@ -357,11 +364,14 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             for (int tau = tid; tau < PR * QS; tau += THREADS) {
                 // tau / PR through the segment's reciprocal: tau < 2^14 and
                 // PR <= 512, so the product is never high and at most one low
-                int qi = (int)((float)tau * inv_pr);
-                int rr = tau - qi * PR;
-                if (rr >= PR) {
-                    ++qi;
-                    rr -= PR;
+                int qi = qi_0, rr = rr_0;
+                if (tau != tid) {
+                    qi = (int)((float)tau * inv_pr);
+                    rr = tau - qi * PR;
+                    if (rr >= PR) {
+                        ++qi;
+                        rr -= PR;
+                    }
                 }
                 const int qr = kpart * QS + qi;
                 const int p = (P == 2 && rr >= R) ? 1 : 0;
