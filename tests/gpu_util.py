@@ -67,19 +67,24 @@ def assert_parity(gpu, ora, tol, what=""):
 _ORACLE_CACHE: dict = {}
 
 
-def oracle_channels(cfg: int, T: int, chans) -> tuple:
+def oracle_channels(cfg: int, T: int, chans=None) -> tuple:
     """Samples of workload ``cfg`` (T spectra, seeded) and the oracle's image
-    cube restricted to ``chans``, cached per process so that the FP32 and FP16
-    full-size tests share one oracle run."""
+    cube restricted to ``chans`` (None: every channel, in one threaded oracle
+    call), cached per process so that the FP32 and FP16 full-size tests share
+    one oracle run."""
     import synth
-    key = (cfg, T, tuple(chans))
+    key = (cfg, T, None if chans is None else tuple(chans))
     if key not in _ORACLE_CACHE:
         sub = synth.workload(cfg).subs[0]
         x = synth.samples(sub, T)
-        ora = np.zeros((sub.n_chan, 4 if sub.n_pol == 2 else 1, sub.grid_n, sub.grid_n))
-        for c in chans:
-            ora[c] = oracle.image(sub, x, chans=range(c, c + 1))[c]
-        _ORACLE_CACHE.clear()   # one full-size workload held at a time
+        if chans is None:
+            ora = oracle.image(sub, x)
+        else:
+            ora = np.zeros((sub.n_chan, 4 if sub.n_pol == 2 else 1, sub.grid_n, sub.grid_n))
+            for c in chans:
+                ora[c] = oracle.image(sub, x, chans=range(c, c + 1))[c]
+        while len(_ORACLE_CACHE) >= 2:   # at most two full-size workloads held at a time
+            _ORACLE_CACHE.pop(next(iter(_ORACLE_CACHE)))
         _ORACLE_CACHE[key] = (sub, x, ora)
     return _ORACLE_CACHE[key]
 

@@ -142,19 +142,14 @@ def test_single_antenna_and_edge_footprint(E):
         assert_parity(gpu, oracle.image(s, x), TOL, f"edge{len(xy)}")
 
 
-def test_full_station_sampled_channels(E):
+def test_full_station_all_channels(E):
     """Config 2 at full size in the benchmark's launch shape (132 channels,
-    1000 spectra in one call), compared on three channels the oracle computes."""
-    sub = synth.workload(2).subs[0]
-    x = synth.samples(sub, 1000)
+    1000 spectra in one call), every channel against the oracle."""
+    sub, x, ora = oracle_channels(2, 1000)
     (gpu,), info = run_library(E, [sub], [x])
-    for c in (0, 77, 131):
-        ora = oracle.image(sub, x, chans=range(c, c + 1))
-        assert_parity(gpu[c:c + 1], ora[c:c + 1], TOL, f"cfg2 full, channel {c}")
-    # every channel: finite, non-negative XX/YY, Cauchy-Schwarz
-    assert np.isfinite(gpu).all()
-    assert (gpu[:, 0] >= 0).all() and (gpu[:, 1] >= 0).all()
-    assert (gpu[:, 2] ** 2 + gpu[:, 3] ** 2 <= gpu[:, 0] * gpu[:, 1] * (1 + 1e-4) + 1e-3).all()
+    fro, mx = assert_parity(gpu, ora, TOL, "cfg2 full, all 132 channels")
+    print(f"cfg2 full: max per-image rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+    check_invariants(gpu)
 
 
 @pytest.mark.parametrize("n,dl,nchan,T,ks", [(256, 0.5, 2, 3, 8), (192, 0.5, 1, 4, 8), (112, 0.75, 2, 5, 2),

@@ -83,7 +83,73 @@ def test_geometry_out_of_grid():
     assert e.value.code == oracle.ORA_E_GEOMETRY
 
 
+def test_geometry_footprint_grows_with_kernel_size():
+    """The footprint is the K x K block centred on the nearest cell: an
+    antenna at cell 29 of a 32-cell grid fits with K = 3 and 5 (cells 27..31)
+    but not with K = 7 (26..32); one at cell 2 fits K = 5 but not K = 7."""
+    for xs, ok in (([6.4], (1, 3, 5)), ([-7.0], (1, 3, 5))):
+        for k in (1, 3, 5, 7):
+            s = Sub([[x, 0.0] for x in xs], grid_n=32, grid_dl=0.5, f0=299792458.0, df=0.0, k=k)
+            if k in ok:
+                cell, _ = oracle.geometry(s)
+                assert cell[0, 0, 0] in (29, 2)
+            else:
+                with pytest.raises(oracle.OracleError) as e:
+                    oracle.geometry(s)
+                assert e.value.code == oracle.ORA_E_GEOMETRY
+
+
 # ---------------------------------------------------------------- taps
+def _gauss_1d(p0, g, k, sigma):
+    """Normalised 1-D Gaussian weights of the k cells p0 - k/2 .. p0 + k/2 at
+    the antenna coordinate g."""
+    d = p0 + np.arange(-(k // 2), k // 2 + 1) - g
+    w = np.exp(-d * d / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 7])
+@pytest.mark.parametrize("sigma", [0.35, 0.5, 0.8])
+def test_gaussian_taps_separable_closed_form(k, sigma):
+    """Any odd K and sigma.  exp(-(ex^2 + ey^2) / (2 s^2)) is the product of a
+    Gaussian in ex and one in ey, and the K x K tap block is the product set
+    of its rows and columns, so the normalised kernel is the outer product of
+    two 1-D Gaussians, each normalised on its own.  At zero sub-cell offset
+    both are exp(-d^2 / (2 s^2)), d = -K/2..K/2, over their sum; K = 1 is a
+    single tap of weight 1."""
+    lam = 1.0                                           # f = c0: one metre per wavelength
+    xy = [[0.0, 0.0], [0.3, -0.45], [-1.2, 2.7]]        # dl = 0.5: two cells per metre
+    s = Sub(xy, n_pol=2, grid_n=32, grid_dl=0.5, f0=299792458.0, df=0.0, k=k)
+    tp = oracle.taps(s, kernel_sigma_cells=sigma)
+    assert tp.shape == (1, 3, 2, k, k)
+    assert np.all(tp.imag == 0)
+    d = np.arange(-(k // 2), k // 2 + 1, dtype=float)
+    w0 = np.exp(-d * d / (2.0 * sigma * sigma))
+    w0 /= w0.sum()
+    np.testing.assert_allclose(tp[0, 0, 0].real, np.outer(w0, w0), rtol=0, atol=1e-15)
+    if k == 1:
+        assert np.all(tp.real == 1.0)
+    for a, (x, y) in enumerate(xy):
+        gx, gy = 16 + 2 * x / lam, 16 + 2 * y / lam
+        px, py = np.floor(gx + 0.5), np.floor(gy + 0.5)
+        expect = np.outer(_gauss_1d(py, gy, k, sigma), _gauss_1d(px, gx, k, sigma))
+        for p in range(2):   # the same kernel for both pols
+            np.testing.assert_allclose(tp[0, a, p].real, expect, rtol=1e-13, atol=1e-16)
+
+
+def test_gaussian_sigma_sets_the_tap_ratio():
+    """At zero offset the ratio of the centre tap to its neighbour is
+    exp(1 / (2 s^2)) for any K: sigma enters squared, in the denominator."""
+    for k in (3, 5, 7):
+        for sigma in (0.35, 0.8, 1.5):
+            s = Sub([[0.0, 0.0]], grid_n=32, grid_dl=0.5, f0=299792458.0, df=0.0, k=k)
+            row = oracle.taps(s, kernel_sigma_cells=sigma)[0, 0, 0].real[k // 2]
+            c = k // 2
+            np.testing.assert_allclose(row[c] / row[c + 1], np.exp(1.0 / (2 * sigma * sigma)), rtol=1e-13)
+            if k > 3:   # distances 1 -> 2: exp((4 - 1) / (2 s^2))
+                np.testing.assert_allclose(row[c + 1] / row[c + 2], np.exp(3.0 / (2 * sigma * sigma)), rtol=1e-13)
+
+
 def test_gaussian_taps_closed_form():
     """Zero sub-cell offset, sigma = 0.5 cell: the 3x3 kernel is the outer
     product of [e^-2, 1, e^-2] / (1 + 2 e^-2) with itself."""
@@ -362,6 +428,14 @@ MUTANTS = {
     "no_norm": ("for (int k = 0; k < K * K; ++k) w[2 * k] /= sum;", "(void)sum;"),
     # rounding to nearest cell replaced by truncation
     "floor": ("double p = floor(gg + 0.5);", "double p = floor(gg);"),
+    # kernel half-width hard-coded to 1 (right only for K = 3)
+    "taps_half_width": ("const int A = s->n_ant, P = s->n_pol, K = s->kernel_k, h = K / 2;",
+                        "const int A = s->n_ant, P = s->n_pol, K = s->kernel_k, h = 1;"),
+    # footprint check with the half-width hard-coded to 1
+    "geometry_half_width": ("const int N = s->grid_n, h = s->kernel_k / 2;", "const int N = s->grid_n, h = 1;"),
+    # sigma ignored (the default 0.5 always)
+    "sigma_fixed": ("double sig = s->kernel_sigma_cells > 0.0 ? s->kernel_sigma_cells : 0.5;",
+                    "double sig = 0.5;"),
 }
 
 
@@ -370,13 +444,16 @@ def _pins_pass() -> bool:
         test_unpack_exhaustive(0)
         test_geometry_special_cases()
         test_gaussian_taps_closed_form()
+        test_gaussian_taps_separable_closed_form(5, 0.8)
+        test_gaussian_taps_separable_closed_form(7, 0.35)
+        test_geometry_footprint_grows_with_kernel_size()
         for ax in (0, 1):
             test_worked_example_closed_form(ax)
         test_fx_identity_dual_pol_user_taps()
         test_autocorr_removed_is_fx_without_diagonal()
         test_polarisation_conjugation_order()
         test_dft_orientation()
-    except (AssertionError, oracle.OracleError):
+    except (AssertionError, oracle.OracleError, pytest.fail.Exception):
         return False
     return True
 
