@@ -227,6 +227,33 @@ epic_status epic_efield(epic_plan_t plan, int32_t sub, const uint8_t* d_samples,
  */
 epic_status epic_set_gains(epic_plan_t plan, int32_t sub, const float* h_gains, void* hip_stream);
 
+/*
+ * epic_image_noalloc -- one whole integration that allocates no device memory,
+ * for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It computes what
+ * epic_grid_fft_accumulate(plan, d_samples, n_time) on zeroed accumulators
+ * followed by epic_readout(plan, d_images, reset) gives, but keeps the partial
+ * accumulators in a static device buffer of the library (at most
+ * EPIC_NOALLOC_MAX_BYTES per GPU, held from the library's first plan on that
+ * GPU until the process ends) instead of the plan's, which it leaves
+ * untouched.  Several sub-arrays run as one launch each (also in plans that
+ * would batch them).
+ *   d_samples   host array [n_sub] of device pointers, as for accumulate.
+ *   n_time      0..max_time (0 writes all-zero images).
+ *   d_images    host array [n_sub] of device pointers, as for epic_readout;
+ *               overwritten.
+ * The buffer is cleared at the start of every call.  Every call on one GPU
+ * shares that GPU's buffer: calls that overlap in time on one GPU (other
+ * streams, other plans, other host threads) race and give wrong images.
+ * Errors: EPIC_E_ARG, EPIC_E_STATE, EPIC_E_DEVICE; EPIC_E_NOMEM when the
+ * plan's partial accumulators for n_time spectra, sum over sub-arrays of
+ * S x C x NPP x N x N floats, exceed EPIC_NOALLOC_MAX_BYTES; EPIC_E_UNSUPPORTED
+ * for plans with EPIC_F_REMOVE_AUTOCORR (whose zero-lag sums are plan state).
+ */
+#define EPIC_NOALLOC_MAX_BYTES (64ll << 20)
+epic_status epic_image_noalloc(epic_plan_t plan, const uint8_t* const* d_samples, int64_t n_time,
+                               float* const* d_images, void* hip_stream);
+
 /* epic_plan_query -- fill *info (host).  Works on dry-run plans.  EPIC_E_ARG on NULL. */
 epic_status epic_plan_query(epic_plan_t plan, epic_plan_info* info);
 

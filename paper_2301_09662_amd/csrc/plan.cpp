@@ -28,6 +28,37 @@ constexpr uint32_t kMagic = 0x45504943u;  // 'EPIC'
 constexpr uint32_t kKnownFlags = EPIC_F_GRAPH | EPIC_F_AUTOTUNE | EPIC_F_DRY_RUN | EPIC_F_REMOVE_AUTOCORR |
                                  EPIC_F_COMPLEX_WEIGHTS | EPIC_F_ONE_LAUNCH;
 
+// ---- static scratch of epic_image_noalloc ----------------------------------
+// Partial accumulators of the allocation-free entry point live in this
+// file-scope device array (EPIC_NOALLOC_MAX_BYTES per GPU, held from module
+// load to process end) instead of plan-owned memory.  Host code never uses the
+// array's name as an address: its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device at plan set-up with that device
+// current.
+constexpr size_t kNoAllocFloats = (size_t)EPIC_NOALLOC_MAX_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current); looked up
+// once per device.
+hipError_t scratch_address(int device, float** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 struct SubHost {
     epic_array_desc desc{};
     std::vector<double> ant_xy;      // [A][2]
@@ -515,6 +546,9 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         int cu = 0;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cu > 0)
             p->num_cu = cu;
+        // the allocation-free entry point's scratch address on this device
+        float* sp = nullptr;
+        if ((e = scratch_address(p->device, &sp)) != hipSuccess) return hip_status(e);
     }
     for (SubHost& h : p->subs) h.dev.precision = desc->precision;
     if (desc->precision == EPIC_FP16 && desc->n_sub > 1) {
@@ -729,6 +763,47 @@ epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, v
         if (e != hipSuccess) return check_device(p, e);
     }
     return EPIC_OK;
+}
+
+epic_status epic_image_noalloc(epic_plan_t p, const uint8_t* const* d_samples, int64_t n_time,
+                               float* const* d_images, void* hip_stream) {
+    if (!valid_plan(p)) return EPIC_E_ARG;
+    if (p->dry_run || p->sticky != EPIC_OK) return EPIC_E_STATE;
+    if (n_time < 0 || n_time > p->desc.max_time) return EPIC_E_ARG;
+    if (!d_samples || !d_images) return EPIC_E_ARG;
+    for (size_t k = 0; k < p->subs.size(); ++k)
+        if (!d_images[k] || (n_time > 0 && !d_samples[k])) return EPIC_E_ARG;
+    if (p->desc.flags & EPIC_F_REMOVE_AUTOCORR) return EPIC_E_UNSUPPORTED;
+    // partial accumulators of this call: each sub-array's slots for n_time
+    // spectra in its dedicated launch, packed into the static scratch
+    std::vector<SubDev> run(p->subs.size());
+    std::vector<size_t> off(p->subs.size());
+    size_t need = 0;
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        SubDev d = p->subs[k].dev;
+        d.S = choose_slots(d, std::max<int64_t>(n_time, 1));
+        d.vaa = nullptr;
+        off[k] = need;
+        need += ((size_t)d.S * d.C * d.NPP * d.N * d.N + 63) & ~(size_t)63;   // 256-byte aligned pieces
+        run[k] = d;
+    }
+    if (need > kNoAllocFloats) return EPIC_E_NOMEM;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
+    float* base = nullptr;
+    hipError_t e = scratch_address(p->device, &base);
+    if (e != hipSuccess) return check_device(p, e);
+    for (size_t k = 0; k < run.size(); ++k) run[k].slots = base + off[k];
+    // clear with a fill kernel (no memset node if the caller captures this)
+    e = launch_zero(base, (int64_t)need, st);
+    for (size_t k = 0; k < run.size() && e == hipSuccess && n_time > 0; ++k) {
+        const SubDev& d = run[k];
+        e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
+                                       : launch_mfma(d, d_samples[k], n_time, st);
+    }
+    for (size_t k = 0; k < run.size() && e == hipSuccess; ++k)
+        e = launch_readout(run[k], d_images[k], p->desc.output == EPIC_OUT_STOKES, 0, st);
+    return check_device(p, e);
 }
 
 epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, void* hip_stream) {

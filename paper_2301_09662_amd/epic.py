@@ -72,6 +72,7 @@ _vp = ctypes.c_void_p
 _lib.epic_plan.argtypes = [_P(epic_plan_desc), _vp, _P(_vp)]
 _lib.epic_grid_fft_accumulate.argtypes = [_vp, _P(_vp), ctypes.c_int64, _vp]
 _lib.epic_readout.argtypes = [_vp, _P(_vp), ctypes.c_int32, _vp]
+_lib.epic_image_noalloc.argtypes = [_vp, _P(_vp), ctypes.c_int64, _P(_vp), _vp]
 _lib.epic_set_gains.argtypes = [_vp, ctypes.c_int32, _P(ctypes.c_float), _vp]
 _lib.epic_efield.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]
 _lib.epic_plan_query.argtypes = [_vp, _P(epic_plan_info)]
@@ -82,11 +83,11 @@ _lib.epic_destroy.argtypes = [_vp]
 _lib.epic_status_str.argtypes = [ctypes.c_int]
 _lib.epic_status_str.restype = ctypes.c_char_p
 _lib.epic_abi_version.argtypes = []
-for _f in ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_efield", "epic_plan_query",
+for _f in ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_image_noalloc", "epic_set_gains", "epic_efield", "epic_plan_query",
            "epic_debug_geometry", "epic_debug_schedule", "epic_debug_unpack", "epic_destroy", "epic_abi_version"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_set_gains", "epic_efield", "epic_plan_query",
+EXPORTED = ("epic_plan", "epic_grid_fft_accumulate", "epic_readout", "epic_image_noalloc", "epic_set_gains", "epic_efield", "epic_plan_query",
             "epic_debug_geometry", "epic_debug_schedule", "epic_debug_unpack", "epic_destroy", "epic_status_str",
             "epic_abi_version")
 
@@ -232,6 +233,24 @@ def epic_readout(plan: Plan, images: Sequence, reset: int = 0, stream=None):
         _check_buffer(t, "float32", int(s.n_chan) * _npp(plan, s) * int(s.grid_n) ** 2, f"images[{k}]")
     ptrs = (_vp * max(len(images), 1))(*[_dev_ptr(t) for t in images])
     _check(_lib.epic_readout(plan, ptrs, int(reset), _stream_handle(stream)), "epic_readout")
+
+
+NOALLOC_MAX_BYTES = 64 << 20   # EPIC_NOALLOC_MAX_BYTES
+
+
+def epic_image_noalloc(plan: Plan, samples: Sequence, n_time: int, images: Sequence, stream=None):
+    """One integration of ``n_time`` spectra straight into ``images[s]``
+    (float32 device tensors [C][NPP][N][N]) with the library's static scratch
+    instead of the plan's accumulators; allocates no device memory."""
+    if len(samples) != len(plan.subs) or len(images) != len(plan.subs):
+        raise ValueError(f"one sample buffer and one image cube per sub-array expected ({len(plan.subs)})")
+    for k, (x, y, s) in enumerate(zip(samples, images, plan.subs)):
+        _check_buffer(x, "uint8", int(n_time) * int(s.n_chan) * int(np.asarray(s.ant_xy).shape[0]) * int(s.n_pol),
+                      f"samples[{k}]")
+        _check_buffer(y, "float32", int(s.n_chan) * _npp(plan, s) * int(s.grid_n) ** 2, f"images[{k}]")
+    xp = (_vp * max(len(samples), 1))(*[_dev_ptr(t) for t in samples])
+    yp = (_vp * max(len(images), 1))(*[_dev_ptr(t) for t in images])
+    _check(_lib.epic_image_noalloc(plan, xp, int(n_time), yp, _stream_handle(stream)), "epic_image_noalloc")
 
 
 def epic_set_gains(plan: Plan, sub: int, gains: Optional[np.ndarray], stream=None):
