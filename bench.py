@@ -6,6 +6,12 @@ over the workload's spectra (unpack, grid, 2D transform, polarisation products,
 accumulate) followed by one epic_readout (ordered reduce + reset).  Inputs are
 resident in HBM before the timed region.  Prints ONE JSON line.
 
+Besides the workload's own form, the reduced-precision legs time the same
+shape with the transforms on the FP16 matrix cores and gridding either as the
+FP32 gather or as a block-sparse product on the matrix cores (FP16 or FP8
+operands).  The FP64 oracle, timed on the host's cores, also gives every form's
+per-channel image error over the same spectra.
+
 Workload (default): the station-scale FP32 configuration -- 256 dual-pol
 antennas in a 100 m x 110 m ellipse, 132 channels of 25 kHz from 40 MHz, 64x64
 grid at 1 wavelength, 3x3 kernels, 1000 spectra (40 ms) per step, seeded
@@ -28,9 +34,10 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector, published (packed issue)
-FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP16_MFMA_PEAK_TFLOPS = 2500.0
+FP8_MFMA_PEAK_TFLOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
+TOL = {"fp32": 1e-5, "fp16": 1e-3, "fp8": 1e-3}
 
 
 def algorithmic_flops_per_ct(sub) -> float:
@@ -48,7 +55,9 @@ def algorithmic_flops_per_ct(sub) -> float:
 # profiles/traffic.json is reported only while their hash still matches.
 KERNEL_SOURCES = {
     "fp32": ["kernels_fp32.hip", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp", "epic_internal.hpp"],
-    "fp16": ["kernels_mfma.hip", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp", "epic_internal.hpp"],
+    "fp16": ["kernels_mfma.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp",
+             "epic_internal.hpp"],
+    "bgemm": ["kernels_bgemm.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_sched.hpp", "epic_internal.hpp"],
 }
 
 
@@ -61,18 +70,25 @@ def sources_sha256(precision):
     return h.hexdigest()
 
 
-def counter_traffic(precision, workload):
-    """HBM bytes per launch of the hot kernel from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs (scaled by the plain-copy calibration), or None
-    when there are none for this workload or the kernel changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def counter_entry(precision, workload, table="traffic.json"):
+    """The committed counter summary of the hot kernel of `precision` on
+    `workload` (profiles/<table>), or None when there is none or the kernel's
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", table)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         entry = json.load(fh).get("kernels", {}).get(f"{precision}:{workload}")
     if not entry or entry.get("sources_sha256") != sources_sha256(precision):
         return None
-    return entry["bytes_per_launch"]
+    return entry
+
+
+def counter_traffic(precision, workload):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs
+    (scaled by the plain-copy calibration), or None."""
+    e = counter_entry(precision, workload)
+    return None if e is None else e["bytes_per_launch"]
 
 
 MFMA_FLOPS = 2 * 16 * 16 * 32     # one v_mfma_f32_16x16x32_f16
@@ -103,12 +119,32 @@ def mfma_ops_per_spectrum(plan, subs):
     return total
 
 
+def grid_mfma_per_call(info, subs, T):
+    """MFMA 16x16x32 instructions of the gridding product of a GEMM-gridding
+    plan: per column part and channel, each block entry is multiplied once per
+    step of grid_step spectra and per split term (FP16 2, FP8 3)."""
+    total = 0
+    for k, s in enumerate(subs):
+        if info["grid_form"][k] == 1:
+            continue
+        terms = 3 if info["precision"] == 2 else 2
+        steps = -(-T // info["grid_step"][k])
+        total += info["col_split"][k] * info["grid_blocks"][k] * terms * steps
+    return total
+
+
 def mfma_fraction(info, kern_ms):
-    """Executed FP16 MFMA rate of a matrix-core call against the dense peak."""
+    """Executed MFMA rate of a matrix-core call against the dense peaks: the
+    FP16 transform products, and the gridding product (FP16 or FP8)."""
     ops = info["mfma_ops_per_call"]
-    tflops = ops * MFMA_FLOPS / (kern_ms * 1e-3) / 1e12
-    return {"executed_ops_per_call": ops, "executed_tflops": tflops, "peak": FP16_MFMA_PEAK_TFLOPS,
-            "frac": tflops / FP16_MFMA_PEAK_TFLOPS, "source": "tile counts of the plan's shapes"}
+    gops = info.get("grid_mfma_per_call", 0)
+    t_tf = ops * MFMA_FLOPS / (kern_ms * 1e-3) / 1e12
+    t_g = gops * MFMA_FLOPS / (kern_ms * 1e-3) / 1e12
+    gpeak = FP8_MFMA_PEAK_TFLOPS if info["precision"] == 2 else FP16_MFMA_PEAK_TFLOPS
+    return {"executed_ops_per_call": ops, "executed_tflops": t_tf, "peak": FP16_MFMA_PEAK_TFLOPS,
+            "frac": t_tf / FP16_MFMA_PEAK_TFLOPS, "grid_ops_per_call": gops, "grid_tflops": t_g,
+            "grid_peak": gpeak, "frac_total": t_tf / FP16_MFMA_PEAK_TFLOPS + t_g / gpeak,
+            "source": "tile counts of the plan's shapes (transforms: counter-checked)"}
 
 
 def rel_image_errors(img, ref):
@@ -125,9 +161,11 @@ def rel_image_errors(img, ref):
     return out
 
 
-def cpu_baseline(sub, samples, budget_s=15.0):
-    """Time the FP64 oracle on a bounded sample of the same workload: all
-    channels over the first T_s spectra, T_s sized for ~budget_s of wall time."""
+def cpu_baseline(sub, samples, budget_s=30.0):
+    """Time the FP64 oracle on the workload: all channels over the first T_s
+    spectra, every spectrum when that fits ~budget_s of wall time (the station
+    does, in ~15 s on 16 cores).  Returns the JSON record and the oracle's
+    image of those spectra, the reference of the parity figures."""
     import oracle
     oracle.build(force=False)
     cores = len(os.sched_getaffinity(0))
@@ -137,12 +175,13 @@ def cpu_baseline(sub, samples, budget_s=15.0):
     dt = time.perf_counter() - t0
     T_s = int(max(probe_t, min(samples.shape[0], budget_s / max(dt, 1e-6) * probe_t)))
     t0 = time.perf_counter()
-    oracle.image(sub, samples[:T_s], n_threads=cores)
+    ref = oracle.image(sub, samples[:T_s], n_threads=cores)
     wall = time.perf_counter() - t0
     n = sub.n_ant * sub.n_pol * sub.n_chan * T_s
-    return {"value": n / wall, "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"all {sub.n_chan} channels x first {T_s} of {samples.shape[0]} spectra "
-                      f"({wall:.1f} s wall, FP64 C loops, OpenMP over channels)"}
+    rec = {"value": n / wall, "unit": "samples/s", "cores": cores, "kind": "oracle",
+           "sample": f"all {sub.n_chan} channels x {'all' if T_s == samples.shape[0] else 'first'} {T_s} of "
+                     f"{samples.shape[0]} spectra ({wall:.1f} s wall, FP64 C loops, OpenMP over channels)"}
+    return rec, ref, T_s
 
 
 def numpy_fft_image(sub, x, c):
@@ -209,7 +248,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cfg", type=int, default=2, help="workload config (default: station FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-reduced", action="store_true", help="skip the FP16 matrix-core leg")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-precision legs")
+    ap.add_argument("--legs", default="fp16:gather,fp16:block,fp8:block",
+                    help="reduced-precision legs of an FP32 workload, precision:gridder, comma-separated")
+    ap.add_argument("--gridder", choices=["auto", "gather", "dense", "block"], default="auto",
+                    help="gridding form of the workload's own run")
     ap.add_argument("--precision", choices=["fp32", "fp16", "fp8"], default=None,
                     help="override the workload's own precision")
     ap.add_argument("--no-graph", action="store_true", help="batched workloads: eager launches instead of graph replay")
@@ -245,8 +288,8 @@ def main():
     samples_per_step = sum(s.n_ant * s.n_pol * s.n_chan * T for s in subs)
     flops_per_launch = sum(algorithmic_flops_per_ct(s) * s.n_chan * T for s in subs)
 
-    def run(precision, steps, warmup, flags=0):
-        plan = E.epic_plan(subs, precision=precision, max_time=T, flags=flags)
+    def run(precision, steps, warmup, flags=0, gridder="auto"):
+        plan = E.epic_plan(subs, precision=precision, max_time=T, flags=flags, gridder=gridder)
         info = E.epic_plan_query(plan)
         outs = [torch.empty((s.n_chan, info["npp"][k], s.grid_n, s.grid_n), dtype=torch.float32, device=dev)
                 for k, s in enumerate(subs)]
@@ -269,20 +312,44 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-        if precision == "fp16":
-            info = dict(info, mfma_ops_per_call=mfma_ops_per_spectrum(plan, subs) * T)
+        if precision != "fp32":
+            info = dict(info, mfma_ops_per_call=mfma_ops_per_spectrum(plan, subs) * T,
+                        grid_mfma_per_call=grid_mfma_per_call(info, subs, T))
+        img = [o.double().cpu().numpy() for o in outs]
+        if T_par is not None and T_par != T:     # the images the oracle's spectra give
+            E.epic_grid_fft_accumulate(plan, [x[:T_par] for x in d_samples], T_par, stream)
+            E.epic_readout(plan, outs, 1, stream)
+            torch.cuda.synchronize()
+            img = [o.double().cpu().numpy() for o in outs]
         E.epic_destroy(plan)
-        return wall / steps * 1e3, kern_ms, [o.double().cpu().numpy() for o in outs], info
+        return wall / steps * 1e3, kern_ms, img, info
+
+    # the FP64 oracle first (timed on the host's cores): its image of the
+    # first T_par spectra is the reference of every form's parity figures
+    cpu = ref = None
+    T_par = None
+    if not args.no_cpu_baseline:
+        cpu, ref, T_par = cpu_baseline(subs[0], host[0])
+
+    def parity(img, prec):
+        """Per-channel relative image error of sub-array 0 against the oracle."""
+        if ref is None:
+            return None
+        e = rel_image_errors(img[0], ref).max(axis=1)
+        return {"max": float(e.max()), "median": float(np.median(e)), "bar": TOL[prec],
+                "ok": bool(e.max() <= TOL[prec]),
+                "per_channel": [float(f"{v:.3g}") for v in e]}
 
     # each workload's own precision; the uneven batch of sub-arrays runs as
     # one autotuned persistent launch replayed from a hipGraph
-    # the large array's FP8 form is not built: its reduced-precision leg is FP16
-    precision = args.precision or ("fp16" if wl.precision == "fp8" else wl.precision)
+    precision = args.precision or wl.precision
     flags = 0
     if len(subs) > 1:
         flags = E.EPIC_F_AUTOTUNE | (0 if args.no_graph else E.EPIC_F_GRAPH)
-    ms_per_step, kern_ms, img32, info32 = run(precision, args.steps, args.warmup, flags)
+    ms_per_step, kern_ms, img32, info32 = run(precision, args.steps, args.warmup, flags, args.gridder)
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
+    dtype = {"fp32": "f32", "fp16": "f16 operands, f32 accumulate",
+             "fp8": "e4m3 gridding operands, f16 transforms, f32 accumulate"}[precision]
     res = {
         "metric": "imaged E-field samples/s (ant*chan*pol*t)",
         "value": samples_per_step / (ms_per_step * 1e-3),
@@ -294,43 +361,56 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if precision == "fp32" else "f16 operands, f32 accumulate",
+        "dtype": dtype,
         "data": "synthetic (seeded 4+4-bit noise + point sources, LWA-station shapes)",
         "config": {"workload": f"{wl.name}: " + "; ".join(
             f"{s.n_ant} ant x {s.n_pol} pol, {s.n_chan} ch, N={s.grid_n}, dl={s.grid_dl}" for s in subs)
             + f", T={T} spectra per step", "n_time": T, "precision": precision,
             "plan": {k: info32[k] for k in ("batched", "can_batch", "form_ms", "autotuned", "graph", "weight",
-                                            "slots", "lds_bytes")}},
+                                            "slots", "lds_bytes", "grid_form", "grid_step")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": counter_traffic(precision, wl.name),
-                     "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch,
-                     "frac_of_nonpacked_issue": achieved / FP32_NONPACKED_TFLOPS},
+                     "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch},
     }
     if res["roofline"]["traffic"] is not None:
         res["roofline"]["hbm_frac"] = res["roofline"]["traffic"] / (kern_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
-    if precision == "fp16":
-        # matrix-core form: the kernel is issue bound on its vector work
-        # (gathering, FP16 packing, products); executed MFMA work for context
+    valu = counter_entry(precision, wl.name, "valu.json")
+    if valu is not None:
+        # floating-point work the kernel executes, from the VALU instruction
+        # counters (lanes x flop per instruction), at the measured time
+        ex = valu["fp_flops_per_launch"] / (kern_ms * 1e-3) / 1e12
+        res["roofline"]["executed_fp32"] = {"tflops": ex, "frac_of_peak": ex / FP32_PEAK_TFLOPS,
+                                            "flops_per_launch": valu["fp_flops_per_launch"],
+                                            "profile": valu["profile"]}
+    if precision != "fp32":
         res["roofline"]["mfma"] = mfma_fraction(info32, kern_ms)
-    red_form = not args.no_reduced and precision == "fp32"
-    if red_form:
-        try:
-            ms16, kern16, img16, info16 = run("fp16", args.steps, args.warmup)
-        except E.EpicError as err:   # no matrix-core kernel for this grid size
-            res["reduced_precision"] = {"precision": "fp16", "unavailable": str(err)}
-            red_form = False
-    if red_form:
-        # error of the FP16 form per image against the FP32 result (all channels);
-        # its parity with the FP64 oracle is the tests' business
-        errs = [rel_image_errors(a, b).max() for a, b in zip(img16, img32)]
-        red = {"precision": "fp16", "value": samples_per_step / (ms16 * 1e-3), "ms_per_step": ms16,
-               "kernel_ms": kern16, "speedup_vs_fp32": ms_per_step / ms16,
-               "max_rel_image_err_vs_fp32_all_channels": float(max(errs)),
-               "achieved_algorithmic_tflops": flops_per_launch / (kern16 * 1e-3) / 1e12,
-               "mfma": mfma_fraction(info16, kern16)}
-        res["reduced_precision"] = red
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(subs[0], host[0])
+    par = {"reference": None if ref is None else
+           f"FP64 oracle, all {subs[0].n_chan} channels x {T_par} spectra of sub-array 0"}
+    par[f"{precision}:{args.gridder}"] = parity(img32, precision)
+    if not args.no_reduced and precision == "fp32":
+        legs = []
+        for leg in [x for x in args.legs.split(",") if x]:
+            lp, lg = leg.split(":")
+            try:
+                ms_l, kern_l, img_l, info_l = run(lp, args.steps, args.warmup, 0, lg)
+            except E.EpicError as err:   # no kernel for this shape / form
+                legs.append({"form": leg, "unavailable": str(err)})
+                continue
+            p = parity(img_l, lp)
+            par[leg] = p
+            legs.append({"form": leg, "precision": lp, "gridder": lg, "grid_step": info_l["grid_step"],
+                         "value": samples_per_step / (ms_l * 1e-3), "ms_per_step": ms_l, "kernel_ms": kern_l,
+                         "speedup_vs_fp32": ms_per_step / ms_l,
+                         "max_rel_image_err_vs_oracle": None if p is None else p["max"],
+                         "achieved_algorithmic_tflops": flops_per_launch / (kern_l * 1e-3) / 1e12,
+                         "mfma": mfma_fraction(info_l, kern_l)})
+        ok = [x for x in legs if "value" in x and (x["max_rel_image_err_vs_oracle"] or 0.0) <= 1e-3]
+        best = max(ok, key=lambda x: x["value"]) if ok else None
+        res["reduced_precision"] = {"legs": legs, "best": None if best is None else best["form"],
+                                    "best_speedup_vs_fp32": None if best is None else best["speedup_vs_fp32"]}
+    res["parity"] = par
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
         res["cpu_numpy_fft"] = cpu_numpy_fft(subs[0], host[0])
     print(json.dumps(res), flush=True)
 

@@ -50,18 +50,23 @@ typedef enum {
 /* Arithmetic of the grid / transform stages.  Accumulation is always FP32. */
 typedef enum {
     EPIC_FP32 = 0,   /* FP32 vector ALU: gather gridding + register FFT */
-    EPIC_FP16 = 1,   /* FP16 matrix cores (MFMA) for the transform stages */
-    EPIC_FP8 = 2     /* FP8 e4m3 matrix cores for gridding, FP16 transforms.
-                        Not built: epic_plan returns EPIC_E_UNSUPPORTED */
+    EPIC_FP16 = 1,   /* FP16 matrix cores (MFMA) for the transform stages; gridding as
+                        the FP32 gather or as an FP16 product (hi + lo weights) */
+    EPIC_FP8 = 2     /* gridding as an FP8 e4m3 product on the matrix cores (4-bit
+                        samples exact in e4m3, weights as a scaled e4m3 hi + lo pair),
+                        FP16 transforms; needs a GEMM gridder (AUTO selects BLOCK_GEMM) */
 } epic_precision;
 
 /* How the gridding step (Eq. 4, W_a * E_a summed over antennas) runs. */
 typedef enum {
-    EPIC_GRID_AUTO = 0,        /* library choice (the gather) */
+    EPIC_GRID_AUTO = 0,        /* library choice: the gather (FP32, FP16), BLOCK_GEMM (FP8) */
     EPIC_GRID_GATHER = 1,      /* each aperture cell sums its antenna list (FP32 ALU) */
-    EPIC_GRID_DENSE_GEMM = 2,  /* kernel matrix x E-field GEMM on matrix cores (not built:
-                                  EPIC_E_UNSUPPORTED) */
-    EPIC_GRID_BLOCK_GEMM = 3   /* block-sparse GEMM (not built: EPIC_E_UNSUPPORTED) */
+    EPIC_GRID_DENSE_GEMM = 2,  /* kernel matrix [window cells x antennas] times the fields
+                                  [antennas x (spectrum, pol, re/im)] on the matrix cores,
+                                  every (16-cell tile, 32-antenna block) multiplied */
+    EPIC_GRID_BLOCK_GEMM = 3   /* the same product over the non-zero blocks only.  Both GEMM
+                                  forms: FP16 / FP8 plans, real weights equal for both pols
+                                  (else EPIC_E_UNSUPPORTED), one launch per sub-array */
 } epic_gridder;
 
 /* Output products per pixel. */
@@ -71,10 +76,15 @@ typedef enum {
 } epic_output;
 
 enum {
-    EPIC_F_GRAPH = 1u,            /* replay accumulate steps from a captured hipGraph */
+    EPIC_F_GRAPH = 1u,            /* replay accumulate steps from captured hipGraphs, one per
+                                     (n_time, input pointers); the 4 most recent are kept */
     EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time */
     EPIC_F_DRY_RUN = 4u,          /* validate and size on the CPU; touch no device */
-    EPIC_F_REMOVE_AUTOCORR = 8u,  /* subtract each antenna's own power term (a = b) at read-out */
+    EPIC_F_REMOVE_AUTOCORR = 8u,  /* subtract each antenna's own power term (a = b) at read-out.
+                                     Its zero-lag sums are exact int32 integers; an accumulate
+                                     call that would take them past 2^24 - 1 spectra first
+                                     folds them into the FP32 lag sums (also done by every
+                                     read-out and epic_set_gains) */
     EPIC_F_COMPLEX_WEIGHTS = 16u, /* gather with complex weights even if every tap is real, so that
                                      epic_set_gains may pass complex (phase) gains later */
     EPIC_F_ONE_LAUNCH = 32u       /* several FP16 sub-arrays: always one persistent launch for all of
@@ -151,6 +161,14 @@ typedef struct {
     int32_t workgroups[16];        /* persistent workgroups of the sub-array's launch */
     int32_t can_batch;             /* 1 if the one-launch form exists for these sub-arrays */
     double form_ms[2];             /* autotuner: probe call time, one launch / one per sub-array */
+    int32_t grid_form[16];         /* epic_gridder each sub-array's kernel runs */
+    int32_t grid_step[16];         /* spectra per gridding product (1 for the gather) */
+    int32_t graph_builds;          /* EPIC_F_GRAPH: graphs captured so far */
+    int32_t autocorr_pending[16];  /* EPIC_F_REMOVE_AUTOCORR: spectra in the zero-lag sums
+                                      since their last fold */
+    int32_t autocorr_fold_limit;   /* the count at which they are folded before a call */
+    int64_t grid_blocks[16];       /* GEMM gridding: (tile, antenna block) products per spectrum
+                                      step and column part, summed over channels */
 } epic_plan_info;
 
 /*
@@ -191,7 +209,9 @@ epic_status epic_grid_fft_accumulate(epic_plan_t plan, const uint8_t* const* d_s
  *               float [C_s][NPP_s][N_s][N_s], indexed [c][product][j][i]
  *               (j: m axis, i: l axis).  Products: EPIC_OUT_POL dual pol
  *               XX*, YY*, Re XY*, Im XY*; single pol XX*; EPIC_OUT_STOKES
- *               I = XX*+YY*, Q = XX*-YY*, U = 2 Re XY*, V = -2 Im XY*.
+ *               I = XX*+YY*, Q = XX*-YY*, U = 2 Re XY*, V = 2 Im XY*
+ *               (linear feeds, XY* = (U + iV)/2: a field with E_Y = -i E_X
+ *               has V = +I, one with E_Y = +i E_X has V = -I).
  *               Overwritten; must stay valid until the stream passes the call.
  *   reset       non-zero: zero the accumulators after reading.
  * Errors: EPIC_E_ARG, EPIC_E_STATE, EPIC_E_DEVICE.

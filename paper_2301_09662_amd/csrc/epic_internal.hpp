@@ -40,6 +40,19 @@ struct ChanInfo {
 // (row * pitch + col) | (groups << 16); y = first group (channel-relative).
 using CellDesc = uint2;
 
+// Operand types of the GEMM-gridding form (gridding on the matrix cores).
+constexpr int kBgFp16 = 0, kBgFp8 = 1;
+
+// GEMM-gridding tables of one channel: its cell tiles (16 non-empty window
+// cells each, in raster order) and the (tile, antenna block) pairs it
+// multiplies -- the non-zero ones (block-sparse form) or all of them (dense).
+struct BgChan {
+    int32_t tile_off;    // first tile of this channel in the tile and cell tables
+    int32_t n_tile;
+    int32_t ent_off;     // first block entry of this channel
+    int32_t n_ent;
+};
+
 // Device resources of one sub-array.
 struct SubDev {
     // shape
@@ -64,7 +77,7 @@ struct SubDev {
     float* gains_buf = nullptr;   // device storage of the gains once any were set
     float2* twiddle;          // [N] exp(+2 pi i r / N)
     float* slots;             // [S][C][NPP][N][N] partial accumulators
-    float* vaa = nullptr;     // [C][A][4 or 1] zero-lag antenna correlations (autocorrelation removal)
+    int32_t* vaa = nullptr;   // [C][A][4 or 1] zero-lag antenna correlations (autocorrelation removal)
     float* lag = nullptr;     // [C][(2K-1)^2][3 or 1][2] lag sums of the autocorrelation image
     // launch shape
     int threads;
@@ -75,6 +88,22 @@ struct SubDev {
     int precision;       // epic_precision of this sub-array's kernel
     int KK;              // 32-deep MFMA steps per transform product
     void* dft16;         // [2N][32 KK] FP16 real-form DFT matrix
+    // gridding on the matrix cores (EPIC_GRID_DENSE_GEMM / EPIC_GRID_BLOCK_GEMM)
+    int gridder = EPIC_GRID_GATHER;   // gridding form this sub-array's kernel runs
+    int R4max = 0;                    // largest window row count, rounded up to 4
+    int bg_tb = 1;                    // spectra per gridding step
+    int bg_nablk = 0;                 // antenna blocks of 32
+    int64_t bg_nentries = 0;          // gather entries (length of bg_dst)
+    int64_t bg_nent = 0;              // block entries over all channels
+    BgChan* bg_chans = nullptr;       // [C]
+    uint2* bg_tiles = nullptr;        // [tiles] (first block entry, channel-relative; block count)
+    uint16_t* bg_cells = nullptr;     // [tiles][16] (r << 8 | w), 0xFFFF padding
+    uint16_t* bg_ents = nullptr;      // [entries] antenna block of each block entry
+    int32_t* bg_perm = nullptr;       // [A] antenna at raster position s
+    int32_t* bg_dst = nullptr;        // [gather entries] operand element of each entry, -1 padding
+    unsigned char* bg_w = nullptr;    // [terms][entries][64 lanes][8] split weights, high part first
+    int bg_nterm = 2;                 // terms of the split (FP16: 2, FP8: 3)
+    float* bg_scale = nullptr;        // [2] FP8 weight scale and its inverse
 };
 
 // One sub-array as seen by the batched (several sub-arrays in one launch)
@@ -116,6 +145,12 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
 hipError_t mfma_configure(SubDev& d, int device, int num_cu);
 hipError_t launch_dft_matrix(const SubDev& d, hipStream_t st);
 hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
+
+// Gridding on the matrix cores (kernels_bgemm.hip): launch shape, the split
+// operand weights (after launch_entry_weights), and the hot path.
+hipError_t bg_configure(SubDev& d, int device, int num_cu);
+hipError_t launch_bg_weights(const SubDev& d, hipStream_t st);
+hipError_t launch_bgemm(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 
 // Several FP16 sub-arrays in one persistent launch.
 hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, int num_cu);

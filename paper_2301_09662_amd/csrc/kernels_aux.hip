@@ -1,6 +1,7 @@
 // One-off FP64 set-up kernels (kernel taps, transform tables, gather-entry
-// weights), the ordered read-out of the partial accumulators, and the debug
-// decoder.  FP64 appears only here, never on the per-spectrum path.
+// weights), the zero-lag correlations and ordered read-out of the partial
+// accumulators, and the debug decoder.  FP64 appears only in the set-up
+// kernels, never on the per-spectrum or per-integration path.
 #include "epic_internal.hpp"
 #include "epic_device.hpp"
 #include "epic_gather.hpp"
@@ -91,34 +92,40 @@ __global__ void entry_weights_kernel(const ChanInfo* __restrict__ chans, const u
 // Zero-lag correlations of every antenna over the spectra of a call:
 // vaa[c][a] += (XX*, YY*, Re XY*, Im XY*) (single pol: XX* only).  One thread
 // per (channel, antenna) sums kAutoChunk spectra in registers and adds them
-// with one atomic per product.  All values are integers below 2^24 (products
-// of 4-bit numbers, at most 128 per spectrum), so the FP32 sums are exact and
-// do not depend on the order of the atomics while a sum stays below 2^24
-// (131072 spectra at full scale between read-outs).
+// with one integer atomic per product.  Every term is an integer of magnitude
+// at most 128 (products of 4-bit numbers), so the int32 sums are exact and
+// independent of the order of the atomics up to 2^24 - 1 spectra; the host
+// folds them into the lag sums before a call would pass that count.
 constexpr int kAutoChunk = 64;
 
+__device__ __forceinline__ int2 unpack44_int(uint32_t byte, int order) {
+    const int hi = ((int)(byte << 24)) >> 28;
+    const int lo = ((int)(byte << 28)) >> 28;
+    return order == 0 ? make_int2(hi, lo) : make_int2(lo, hi);
+}
+
 __global__ void autocorr_accumulate_kernel(const uint8_t* __restrict__ samples, int64_t T, int C, int A, int P,
-                                           int nibble_order, float* __restrict__ vaa) {
+                                           int nibble_order, int32_t* __restrict__ vaa) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // c * A + a
     if (idx >= (int64_t)C * A) return;
     const int64_t c = idx / A, a = idx - c * A;
     const int64_t t0 = (int64_t)blockIdx.y * kAutoChunk;
     const int64_t t1 = (t0 + kAutoChunk < T) ? t0 + kAutoChunk : T;
     const int64_t AP = (int64_t)A * P;
-    float xx = 0.f, yy = 0.f, xyr = 0.f, xyi = 0.f;
+    int xx = 0, yy = 0, xyr = 0, xyi = 0;
     for (int64_t t = t0; t < t1; ++t) {
         const uint8_t* row = samples + (t * C + c) * AP + a * P;
-        const float2 x = unpack44(row[0], nibble_order);
-        xx = fmaf(x.x, x.x, fmaf(x.y, x.y, xx));
+        const int2 x = unpack44_int(row[0], nibble_order);
+        xx += x.x * x.x + x.y * x.y;
         if (P == 2) {
-            const float2 y = unpack44(row[1], nibble_order);
-            yy = fmaf(y.x, y.x, fmaf(y.y, y.y, yy));
-            xyr = fmaf(x.x, y.x, fmaf(x.y, y.y, xyr));
-            xyi = fmaf(x.y, y.x, fmaf(-x.x, y.y, xyi));
+            const int2 y = unpack44_int(row[1], nibble_order);
+            yy += y.x * y.x + y.y * y.y;
+            xyr += x.x * y.x + x.y * y.y;
+            xyi += x.y * y.x - x.x * y.y;
         }
     }
     const int npa = (P == 2) ? 4 : 1;
-    float* dst = vaa + idx * npa;
+    int32_t* dst = vaa + idx * npa;
     atomicAdd(dst, xx);
     if (P == 2) {
         atomicAdd(dst + 1, yy);
@@ -133,23 +140,23 @@ __global__ void autocorr_accumulate_kernel(const uint8_t* __restrict__ samples, 
 // kernel image times its conjugate depends on these lags only, not on where
 // the antenna sits, so sum_d R(d) exp(+2 pi i d.k / N) is the image of the
 // a = b terms.  Products: 0 XX* (w^X, w^X), 1 YY* (w^Y, w^Y), 2 XY* (w^X, w^Y).
-// Block (lag, channel); threads stride over antennas; FP64 sums, added into
-// the lag accumulator (which thus holds the a = b terms of several stretches
-// of an integration with different gains).
+// Block (lag, channel); threads stride over antennas; FP32 sums in a fixed
+// order, added into the lag accumulator (which thus holds the a = b terms of
+// several stretches of an integration with different gains).
 // lag layout: [C][L][npl][2] with L = (2K-1)^2, npl = 3 (dual pol) or 1.
-__global__ void autocorr_lag_kernel(const float* __restrict__ vaa, const float* __restrict__ taps,
+__global__ void autocorr_lag_kernel(const int32_t* __restrict__ vaa, const float* __restrict__ taps,
                                     const float* __restrict__ gains, float* __restrict__ lag, int C, int A, int P,
                                     int K) {
     const int L1 = 2 * K - 1;
     const int l = blockIdx.x, c = blockIdx.y;
     const int ddy = l / L1 - (K - 1), ddx = l % L1 - (K - 1);
     const int npl = (P == 2) ? 3 : 1, npa = (P == 2) ? 4 : 1;
-    double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    float acc[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
     for (int a = threadIdx.x; a < A; a += blockDim.x) {
-        const float* v = vaa + ((int64_t)c * A + a) * npa;
+        const int32_t* v = vaa + ((int64_t)c * A + a) * npa;
         for (int q = 0; q < npl; ++q) {
             const int pa = (q == 1) ? 1 : 0, pb = (q == 0) ? 0 : 1;
-            double gr[2] = {1.0, 1.0}, gi[2] = {0.0, 0.0};
+            float gr[2] = {1.f, 1.f}, gi[2] = {0.f, 0.f};
             if (gains)
                 for (int h = 0; h < 2; ++h) {
                     const int p = h ? pb : pa;
@@ -157,7 +164,7 @@ __global__ void autocorr_lag_kernel(const float* __restrict__ vaa, const float* 
                     gr[h] = gains[gix];
                     gi[h] = gains[gix + 1];
                 }
-            double sr = 0.0, si = 0.0;   // sum_u w^pa(u + d) conj(w^pb(u))
+            float sr = 0.f, si = 0.f;   // sum_u w^pa(u + d) conj(w^pb(u))
             for (int uy = 0; uy < K; ++uy) {
                 const int vy = uy + ddy;
                 if (vy < 0 || vy >= K) continue;
@@ -167,22 +174,22 @@ __global__ void autocorr_lag_kernel(const float* __restrict__ vaa, const float* 
                     const float* ta = taps + ((((int64_t)c * A + a) * P + pa) * K * K + vy * K + vx) * 2;
                     const float* tb = taps + ((((int64_t)c * A + a) * P + pb) * K * K + uy * K + ux) * 2;
                     // gains applied to the taps as the gridding does
-                    const double ar = gr[0] * ta[0] - gi[0] * ta[1], ai = gr[0] * ta[1] + gi[0] * ta[0];
-                    const double br = gr[1] * tb[0] - gi[1] * tb[1], bi = gr[1] * tb[1] + gi[1] * tb[0];
+                    const float ar = gr[0] * ta[0] - gi[0] * ta[1], ai = gr[0] * ta[1] + gi[0] * ta[0];
+                    const float br = gr[1] * tb[0] - gi[1] * tb[1], bi = gr[1] * tb[1] + gi[1] * tb[0];
                     sr += ar * br + ai * bi;
                     si += ai * br - ar * bi;
                 }
             }
-            double vr, vi;
-            if (q == 0) { vr = v[0]; vi = 0.0; }
-            else if (q == 1) { vr = v[1]; vi = 0.0; }
-            else { vr = v[2]; vi = v[3]; }
+            float vr, vi;
+            if (q == 0) { vr = (float)v[0]; vi = 0.f; }
+            else if (q == 1) { vr = (float)v[1]; vi = 0.f; }
+            else { vr = (float)v[2]; vi = (float)v[3]; }
             acc[q][0] += vr * sr - vi * si;
             acc[q][1] += vr * si + vi * sr;
         }
     }
     // block reduction (fixed order: deterministic)
-    __shared__ double red[256][6];
+    __shared__ float red[256][6];
     for (int q = 0; q < 3; ++q) {
         red[threadIdx.x][2 * q] = acc[q][0];
         red[threadIdx.x][2 * q + 1] = acc[q][1];
@@ -197,20 +204,23 @@ __global__ void autocorr_lag_kernel(const float* __restrict__ vaa, const float* 
         const int L = L1 * L1;
         float* out = lag + (((int64_t)c * L + l) * npl) * 2;
         for (int q = 0; q < npl; ++q) {
-            out[2 * q] += (float)red[0][2 * q];
-            out[2 * q + 1] += (float)red[0][2 * q + 1];
+            out[2 * q] += red[0][2 * q];
+            out[2 * q + 1] += red[0][2 * q + 1];
         }
     }
 }
 
 // out[c][k][j][i] = sum_s slots[s][c][k][j][i], summed in slot order so the
 // result is identical from run to run; minus the autocorrelation image when
-// lag != nullptr; Stokes form on request (linear feeds: I = XX+YY, Q = XX-YY,
-// U = 2 Re XY*, V = -2 Im XY*); optional reset of the slots.
-// The autocorrelation image at pixel (i, j) reads frequency bin k = (i + N/2,
-// j + N/2) mod N, where exp(+2 pi i d.k / N) = (-1)^(dx+dy) exp(+2 pi i (dx i + dy j) / N).
+// lag != nullptr; Stokes form on request (linear feeds, XY* = (U + i V) / 2:
+// I = XX+YY, Q = XX-YY, U = 2 Re XY*, V = 2 Im XY*); optional reset of the
+// slots.  The autocorrelation image at pixel (i, j) reads frequency bin
+// k = (i + N/2, j + N/2) mod N, where exp(+2 pi i d.k / N) =
+// (-1)^(dx+dy) exp(+2 pi i (dx i + dy j) / N), the phase from the plan's table
+// tw[r] = exp(+2 pi i r / N) (FP64 at plan time, rounded once to FP32).
 __global__ void readout_kernel(float* __restrict__ slots, float* __restrict__ out, int S, int C, int NPP,
-                               int N, int stokes, int reset, const float* __restrict__ lag, int K) {
+                               int N, int stokes, int reset, const float* __restrict__ lag, int K,
+                               const float2* __restrict__ tw) {
     const int NN = N * N;
     const int64_t per_slot = (int64_t)C * NPP * NN;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over C * NN pixels
@@ -228,10 +238,9 @@ __global__ void readout_kernel(float* __restrict__ slots, float* __restrict__ ou
             const int dy = l / L1 - (K - 1), dx = l % L1 - (K - 1);
             int r = (dx * i + dy * j) % N;
             if (r < 0) r += N;
-            double sn, cs;
-            sincospi(2.0 * (double)r / (double)N, &sn, &cs);
+            const float2 ph = tw[r];
             const float sg = ((dx + dy) & 1) ? -1.f : 1.f;
-            const float er = sg * (float)cs, ei = sg * (float)sn;
+            const float er = sg * ph.x, ei = sg * ph.y;
             for (int q = 0; q < npl; ++q) {
                 const float lr = lc[(l * npl + q) * 2], li = lc[(l * npl + q) * 2 + 1];
                 ar[q] = fmaf(lr, er, fmaf(-li, ei, ar[q]));
@@ -246,7 +255,7 @@ __global__ void readout_kernel(float* __restrict__ slots, float* __restrict__ ou
         }
     }
     if (stokes && NPP == 4) {
-        const float I = v[0] + v[1], Q = v[0] - v[1], U = 2.0f * v[2], V = -2.0f * v[3];
+        const float I = v[0] + v[1], Q = v[0] - v[1], U = 2.0f * v[2], V = 2.0f * v[3];
         v[0] = I; v[1] = Q; v[2] = U; v[3] = V;
     }
     for (int k = 0; k < NPP; ++k) out[(c * NPP + k) * NN + pix] = v[k];
@@ -315,7 +324,7 @@ hipError_t launch_autocorr_fold(const SubDev& d, hipStream_t st) {
     autocorr_lag_kernel<<<dim3(L1 * L1, d.C), dim3(256), 0, st>>>(d.vaa, d.taps, d.gains, d.lag, d.C, d.A, d.P, d.K);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_zero(d.vaa, vaa_count(d), st);
+    return launch_zero(reinterpret_cast<float*>(d.vaa), vaa_count(d), st);   // all-zero bits: 0 as int32 too
 }
 
 hipError_t launch_readout(const SubDev& d, float* out, int stokes, int reset, hipStream_t st) {
@@ -324,7 +333,7 @@ hipError_t launch_readout(const SubDev& d, float* out, int stokes, int reset, hi
     hipError_t e = launch_autocorr_fold(d, st);
     if (e != hipSuccess) return e;
     readout_kernel<<<dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st>>>(
-        d.slots, out, d.S, d.C, d.NPP, d.N, stokes, reset, d.vaa ? d.lag : nullptr, d.K);
+        d.slots, out, d.S, d.C, d.NPP, d.N, stokes, reset, d.vaa ? d.lag : nullptr, d.K, d.twiddle);
     e = hipGetLastError();
     if (e != hipSuccess || !reset || !d.vaa) return e;
     return launch_zero(d.lag, lag_count(d), st);

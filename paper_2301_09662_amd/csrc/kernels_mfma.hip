@@ -1,25 +1,11 @@
-// Reduced-precision hot path on the gfx950 matrix cores (MFMA).  Same
-// persistent (channel, spectrum) schedule, decoding and FP32 gather gridding
-// as the FP32 kernel; the two transform passes of Eq. 4 become dense products
-// with the exp(+2 pi i ...) DFT matrix F (FP16 operands, FP32 accumulation):
-//
-//   row pass     Y   = G  F_W      [P*R rows x W]    x [W x N]     per spectrum
-//   column pass  E~  = F_R Y        [N x R]           x [R x N]     per spectrum, pol
-//
-// each written in real form with the 2x2 block matrix M = [[Fr, -Fi], [Fi, Fr]]
-// (so one real product gives both real and imaginary parts), K padded to
-// whole 32-deep MFMA steps (zero cells beyond the aperture window, which sits
-// at the grid origin as in the FP32 kernel).  G and Y are rounded to FP16 as
-// MFMA inputs (4-bit samples times FP32 kernel weights); every accumulation,
-// the polarisation products of Eq. 5 and the time sum stay in FP32.
-//
-// Wave w of a workgroup owns image rows 16w..16w+15 (j, m axis) and all of
-// the workgroup's columns: its M fragments for those rows stay in registers
-// for the whole kernel, and the X and Y outputs of each pixel land in the same
-// lane and register slot, so the products and time sums never leave registers.
-// MFMA 16x16x32 f16 lane layout (verified on the device): A lane l holds
-// A[l%16][8(l/16)+e], B lane l holds B[8(l/16)+e][l%16], D lane l holds
-// D[4(l/16)+e][l%16].
+// Reduced-precision hot path on the gfx950 matrix cores (MFMA), gather
+// gridding.  Same persistent (channel, spectrum) schedule and decoding as the
+// FP32 kernel, and the same FP32 gather gridding; the two transform passes of
+// Eq. 4 become dense products with the exp(+2 pi i ...) DFT matrix (FP16
+// operands, FP32 accumulation) and the products of Eq. 5 are summed in FP32
+// registers -- the shared building blocks are in epic_mfma.hpp.  G and Y are
+// rounded to FP16 as MFMA inputs (4-bit samples times FP32 kernel weights);
+// every accumulation, the polarisation products and the time sum stay in FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,15 +13,12 @@
 #include "epic_device.hpp"
 #include "epic_gather.hpp"
 #include "epic_internal.hpp"
+#include "epic_mfma.hpp"
 #include "epic_sched.hpp"
 
 namespace epic {
 
 namespace {
-
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef _Float16 half4 __attribute__((ext_vector_type(4)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // One sub-array as the segment function sees it.
 struct SegCtx {
@@ -65,35 +48,6 @@ struct MfmaArgs {
     int V;                    // virtual channels C * KS
     int grid_wg, wg_per_xcd;
 };
-
-// Row padding (halfs) of the matrix-core operand buffers in LDS.
-constexpr int kPadH = 8;
-
-template <int N_, int KK_>
-struct MShape {
-    static constexpr int N = N_;
-    static constexpr int KK = KK_;                 // 32-deep MFMA steps per product
-    static constexpr int KPAD = 16 * KK;           // window extent padded (cells)
-    static constexpr int K2 = 2 * KPAD;            // real-form depth: [re | im]
-    static constexpr int KS = (N > 64) ? 2 : 1;    // image columns split over KS workgroups
-    static constexpr int NK = N / KS;              // columns per workgroup
-    static constexpr int IT = NK / 16;             // 16-column tiles per workgroup
-    static constexpr int WAVES = N / 16;           // one wave per 16 image rows
-    static constexpr int NT1 = 2 / KS;             // row-pass output tiles per wave
-    // register budget: three waves per SIMD (168 VGPRs) for the small shapes,
-    // where the extra resident workgroup outweighs a few spills (measured:
-    // station N = 64, KK = 2: 0.75 -> 0.64 ms); the compiler's choice otherwise
-    static constexpr int WAVES_PER_EU = (N <= 64 && KK <= 2) ? 3 : 1;
-    static constexpr int A1P = K2 + kPadH;         // LDS pitches (halfs)
-    static constexpr int B2P = K2 + kPadH;
-};
-
-template <int N_>
-constexpr int mfma_threads() { return 64 * (N_ / 16); }
-
-__device__ __forceinline__ floatx4 mfma16(half8 a, half8 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
 
 // Gather gridding of every non-empty window cell (FP32 sums), stored as the
 // FP16 row-pass operand: row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)].
@@ -155,12 +109,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
 
     // column-pass operand: rows 16w.. (real part) and N + 16w.. (imaginary part)
     half8 a2[2][KK];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int ks = 0; ks < KK; ++ks)
-            a2[h][ks] = *reinterpret_cast<const half8*>(sc.dft + (size_t)(h * N + 16 * mw + l16) * K2 + 32 * ks +
-                                                        8 * l4);
+    load_col_fragments<Sh>(a2, sc.dft, mw, l16, l4);
 
     const int AP = sc.A * P;
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(sc.samples) & 3) == 0);
@@ -223,14 +172,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
         const uint2* g_gant = sc.grp_ant + ci.grp_off;
         const float4* g_w = sc.grp_w + (int64_t)ci.grp_off * GF4;
         half8 b1[NT1][KK];   // row-pass operand for this wave's output tiles
-#pragma unroll
-        for (int u = 0; u < NT1; ++u) {
-            const int nloc = 16 * (mw * NT1 + u) + l16;          // own-column index in [0, 2 NK)
-            const int row = (nloc < NK) ? kpart * NK + nloc : N + kpart * NK + (nloc - NK);
-#pragma unroll
-            for (int ks = 0; ks < KK; ++ks)
-                b1[u][ks] = *reinterpret_cast<const half8*>(sc.dft + (size_t)row * K2 + 32 * ks + 8 * l4);
-        }
+        load_row_fragments<Sh>(b1, sc.dft, kpart, mw, l16, l4);
         __syncthreads();   // the previous segment is done with every LDS buffer
         if (prog) {
             for (int k = tid; k < ci.n_grp * GF4; k += TH) s_w[k] = g_w[k];
@@ -287,87 +229,17 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             __syncthreads();
 
             __builtin_amdgcn_s_setprio(1);
-            // 3a. row pass: [M1 x K2] x [K2 x 2 NK] on the matrix cores; each wave
-            //     takes NT1 output tiles and writes them, rounded to FP16, as the
-            //     column-pass operand B2[p][i][Re Y(0..) | Im Y(0..)]
-            if (mwave) {
-                for (int mt = 0; mt < (M1 + 15) / 16; ++mt) {
-                    half8 af[KK];
-#pragma unroll
-                    for (int ks = 0; ks < KK; ++ks)
-                        af[ks] = *reinterpret_cast<const half8*>(s_A1 + (16 * mt + l16) * A1P + 32 * ks + 8 * l4);
-                    const int m0 = 16 * mt + 4 * l4;
-#pragma unroll
-                    for (int u = 0; u < NT1; ++u) {
-                        floatx4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int ks = 0; ks < KK; ++ks) d = mfma16(af[ks], b1[u][ks], d);
-                        if (m0 < M1) {
-                            const int p = (P == 2 && m0 >= R4) ? 1 : 0;
-                            const int r0 = m0 - p * R4;
-                            const int nloc = 16 * (mw * NT1 + u) + l16;
-                            const int part = nloc >= NK ? 1 : 0;
-                            const int iloc = nloc - part * NK;
-                            half4 hv;
-                            hv[0] = (_Float16)d[0]; hv[1] = (_Float16)d[1];
-                            hv[2] = (_Float16)d[2]; hv[3] = (_Float16)d[3];
-                            *reinterpret_cast<half4*>(s_B2 + (p * NK + iloc) * B2P + part * KPAD + r0) = hv;
-                        }
-                    }
-                }
-            }
+            // 3a. row pass on the matrix cores -> column-pass operand B2
+            if (mwave) row_pass<Sh, P>(s_A1, s_B2, b1, M1, R4, mw, l16, l4);
             __syncthreads();
 
             __builtin_amdgcn_s_setprio(0);
-            // 3b + 4. column pass: E~ rows 16w.. for every own column tile, both
-            //         pols, then the products of Eq. 5 accumulated in registers
-            if (mwave) {
-#pragma unroll
-                for (int it = 0; it < IT; ++it) {
-                    floatx4 er[P], ei[P];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        er[p] = floatx4{0.f, 0.f, 0.f, 0.f};
-                        ei[p] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int ks = 0; ks < KK; ++ks) {
-                            const half8 bf = *reinterpret_cast<const half8*>(
-                                s_B2 + (p * NK + 16 * it + l16) * B2P + 32 * ks + 8 * l4);
-                            er[p] = mfma16(a2[0][ks], bf, er[p]);
-                            ei[p] = mfma16(a2[1][ks], bf, ei[p]);
-                        }
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float xr = er[0][e], xi = ei[0][e];
-                        acc[it][e][0] = fmaf(xr, xr, fmaf(xi, xi, acc[it][e][0]));
-                        if constexpr (P == 2) {
-                            const float yr = er[1][e], yi = ei[1][e];
-                            acc[it][e][1] = fmaf(yr, yr, fmaf(yi, yi, acc[it][e][1]));
-                            acc[it][e][2] = fmaf(xr, yr, fmaf(xi, yi, acc[it][e][2]));
-                            acc[it][e][3] = fmaf(xi, yr, fmaf(-xr, yi, acc[it][e][3]));
-                        }
-                    }
-                }
-            }
+            // 3b + 4. column pass, both pols, products of Eq. 5 into registers
+            if (mwave) col_pass<Sh, P>(s_B2, a2, acc, l16, l4);
         }
 
         // add the segment's sums into its slot; bin -> pixel (+N/2 mod N)
-        if (mwave) {
-            float* base_p = sc.slots + ((int64_t)slot * sc.C + c) * NPP * N * N;
-#pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                int ii = kpart * NK + 16 * it + l16 + N / 2;
-                if (ii >= N) ii -= N;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    int j = 16 * mw + 4 * l4 + e + N / 2;
-                    if (j >= N) j -= N;
-#pragma unroll
-                    for (int k = 0; k < NPP; ++k) base_p[((int64_t)k * N + j) * N + ii] += acc[it][e][k];
-                }
-            }
-        }
+        if (mwave) flush_slot<Sh, P>(sc.slots, slot, sc.C, c, kpart, acc, mw, l16, l4);
         f += n;
         ++s_ch;
         v += vstep;

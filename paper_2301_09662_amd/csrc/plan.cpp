@@ -69,6 +69,13 @@ struct SubHost {
     std::vector<CellDesc> cells_desc;
     std::vector<uint16_t> grp_ant;
     std::vector<uint8_t> grp_tap;
+    // gridding on the matrix cores
+    std::vector<BgChan> bg_chans;
+    std::vector<uint2> bg_tiles;
+    std::vector<uint16_t> bg_cells;
+    std::vector<uint16_t> bg_ents;
+    std::vector<int32_t> bg_perm;
+    std::vector<int32_t> bg_dst;
     SubDev dev{};
 };
 
@@ -94,12 +101,23 @@ struct epic_plan_s {
     std::vector<int> weights;        // cost of one spectrum per sub-array
     std::vector<BatchSub> table;     // host copy of bd.table
     int autotuned = 0;
-    // hipGraph replay of one accumulate step
+    // hipGraph replay of accumulate steps: one executable graph per (spectra
+    // count, input pointers), the kGraphCache most recently used kept
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int64_t graph_T = -1;
-    std::vector<const uint8_t*> graph_ptrs;
+    struct GraphEntry {
+        int64_t T;
+        std::vector<const uint8_t*> ptrs;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        uint64_t last;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    int graph_builds = 0;
+    // autocorrelation removal: spectra in each sub-array's zero-lag sums since
+    // their last fold, and the count at which they are folded first
+    std::vector<int64_t> ac_pending;
+    int64_t ac_limit = 0;
     // host staging of epic_set_gains (pinned, reused once its copy is done)
     float* gain_stage = nullptr;
     size_t gain_stage_n = 0;
@@ -222,6 +240,106 @@ void build_gather(SubHost& h) {
         CellMax = std::max(CellMax, ci.n_cell);
     }
     h.dev.Gmax = Gmax; h.dev.CellMax = CellMax;
+    int r4 = 0;
+    for (const ChanInfo& ci : h.chans) r4 = std::max(r4, (ci.R + 3) & ~3);
+    h.dev.R4max = r4;
+}
+
+// Tables of the GEMM-gridding form (gridding as the product of each channel's
+// kernel matrix with the fields, Eq. 4).  Antennas are taken in raster order
+// of their positions (north, then east; the order of their cells at every
+// channel, up to ties), 32 per block; each channel's non-empty window cells,
+// in raster order, 16 per tile.  For every tile the antenna blocks it
+// multiplies: the ones with a non-zero weight in the tile, or all of them
+// (dense).  Every gather entry (cell, antenna, tap) gets the element of the
+// operand block that holds its weight: entry e of the channel's block list,
+// lane 16 ((s % 32) / 8) + (row of the cell in its tile), position s % 8,
+// with s the antenna's raster position (MFMA A-operand layout).
+epic_status build_bgemm(SubHost& h, bool dense) {
+    const int A = h.desc.n_ant, C = h.desc.n_chan;
+    const int WP = h.dev.WP;
+    std::vector<int32_t> order(A);
+    for (int a = 0; a < A; ++a) order[a] = a;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const double yx = h.ant_xy[2 * x + 1], yy = h.ant_xy[2 * y + 1];
+        if (yx != yy) return yx < yy;
+        return h.ant_xy[2 * x] < h.ant_xy[2 * y];
+    });
+    std::vector<int32_t> pos(A);
+    for (int s = 0; s < A; ++s) pos[order[s]] = s;
+    const int nablk = (A + 31) / 32;
+    h.bg_perm = order;
+    h.bg_chans.assign(C, BgChan{});
+    h.bg_tiles.clear(); h.bg_cells.clear(); h.bg_ents.clear();
+    h.bg_dst.assign(h.grp_ant.size(), -1);
+    int64_t n_ent = 0;
+    std::vector<int> cell_order;
+    std::vector<int> blocks;
+    for (int c = 0; c < C; ++c) {
+        const ChanInfo& ci = h.chans[c];
+        BgChan& bc = h.bg_chans[c];
+        bc.tile_off = (int32_t)(h.bg_tiles.size());
+        bc.ent_off = (int32_t)n_ent;
+        cell_order.resize(ci.n_cell);
+        for (int k = 0; k < ci.n_cell; ++k) cell_order[k] = k;
+        auto offset = [&](int k) { return (int)(h.cells_desc[ci.cell_off + k].x & 0xFFFFu); };
+        std::sort(cell_order.begin(), cell_order.end(), [&](int x, int y) { return offset(x) < offset(y); });
+        const int n_tile = (ci.n_cell + 15) / 16;
+        bc.n_tile = n_tile;
+        int ent_in_chan = 0;
+        for (int i = 0; i < n_tile; ++i) {
+            blocks.clear();
+            for (int rt = 0; rt < 16; ++rt) {
+                const int kk = 16 * i + rt;
+                if (kk >= ci.n_cell) {
+                    h.bg_cells.push_back(0xFFFFu);
+                    continue;
+                }
+                const CellDesc d = h.cells_desc[ci.cell_off + cell_order[kk]];
+                const int off = (int)(d.x & 0xFFFFu), ng = (int)(d.x >> 16);
+                const int r = off / WP, w = off - r * WP;
+                if (r > 255 || w > 255) return EPIC_E_UNSUPPORTED;
+                h.bg_cells.push_back((uint16_t)((r << 8) | w));
+                for (int e = 0; e < ng * kGroup; ++e) {
+                    const size_t ge = ((size_t)ci.grp_off + d.y) * kGroup + e;
+                    if (h.grp_tap[ge] != 255) blocks.push_back(pos[h.grp_ant[ge]] / 32);
+                }
+            }
+            if (dense) {
+                blocks.resize(nablk);
+                for (int j = 0; j < nablk; ++j) blocks[j] = j;
+            } else {
+                std::sort(blocks.begin(), blocks.end());
+                blocks.erase(std::unique(blocks.begin(), blocks.end()), blocks.end());
+            }
+            h.bg_tiles.push_back(make_uint2((uint32_t)ent_in_chan, (uint32_t)blocks.size()));
+            for (int j : blocks) h.bg_ents.push_back((uint16_t)j);
+            // operand element of every gather entry of the tile's cells
+            for (int rt = 0; rt < 16 && 16 * i + rt < ci.n_cell; ++rt) {
+                const CellDesc d = h.cells_desc[ci.cell_off + cell_order[16 * i + rt]];
+                const int ng = (int)(d.x >> 16);
+                for (int e = 0; e < ng * kGroup; ++e) {
+                    const size_t ge = ((size_t)ci.grp_off + d.y) * kGroup + e;
+                    if (h.grp_tap[ge] == 255) continue;
+                    const int sp = pos[h.grp_ant[ge]];
+                    const int q = (int)(std::lower_bound(blocks.begin(), blocks.end(), sp / 32) - blocks.begin());
+                    const int64_t ent = n_ent + ent_in_chan + q;
+                    const int k = sp & 31;
+                    const int64_t el = (ent * 64 + 16 * (k >> 3) + rt) * 8 + (k & 7);
+                    if (el > (int64_t)std::numeric_limits<int32_t>::max()) return EPIC_E_UNSUPPORTED;
+                    h.bg_dst[ge] = (int32_t)el;
+                }
+            }
+            ent_in_chan += (int)blocks.size();
+        }
+        bc.n_ent = ent_in_chan;
+        n_ent += ent_in_chan;
+    }
+    if (n_ent * 512 > (int64_t)std::numeric_limits<int32_t>::max()) return EPIC_E_UNSUPPORTED;
+    h.dev.bg_nablk = nablk;
+    h.dev.bg_nentries = (int64_t)h.grp_ant.size();
+    h.dev.bg_nent = n_ent;
+    return EPIC_OK;
 }
 
 epic_status hip_status(hipError_t e) {
@@ -257,10 +375,13 @@ void free_all(epic_plan_s* p) {
         if (p->gain_ev) (void)hipEventDestroy(p->gain_ev);
         if (p->gain_stage) (void)hipHostFree(p->gain_stage);
         p->gain_ev = nullptr; p->gain_stage = nullptr;
-        if (p->exec) (void)hipGraphExecDestroy(p->exec);
-        if (p->graph) (void)hipGraphDestroy(p->graph);
+        for (auto& g : p->graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        p->graphs.clear();
         if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-        p->exec = nullptr; p->graph = nullptr; p->cap_stream = nullptr;
+        p->cap_stream = nullptr;
         for (void* v : p->allocations) (void)hipFree(v);
     }
     p->allocations.clear();
@@ -468,6 +589,13 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
     return EPIC_OK;
 }
 
+// The hot kernel of one sub-array in its own launch.
+hipError_t launch_one(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
+    if (d.precision == EPIC_FP32) return launch_fp32(d, samples, n_time, st);
+    if (d.gridder != EPIC_GRID_GATHER) return launch_bgemm(d, samples, n_time, st);
+    return launch_mfma(d, samples, n_time, st);
+}
+
 // The kernel launches of one accumulate step.
 hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
     if (p->batched) {
@@ -476,8 +604,7 @@ hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t 
     } else {
         for (size_t k = 0; k < p->subs.size(); ++k) {
             const SubDev& d = p->subs[k].dev;
-            hipError_t e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
-                                                      : launch_mfma(d, d_samples[k], n_time, st);
+            hipError_t e = launch_one(d, d_samples[k], n_time, st);
             if (e != hipSuccess) return e;
         }
     }
@@ -492,25 +619,74 @@ hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t 
     return hipSuccess;
 }
 
-// Replay the step from a captured hipGraph; re-capture when the spectra
-// count or the input pointers change.
+// Replay the step from a captured hipGraph.  Each (spectra count, input
+// pointers) gets its own executable graph; the kGraphCache most recently used
+// are kept, so a caller that rotates over a few input buffers replays instead
+// of capturing again.
+constexpr size_t kGraphCache = 4;
+
 hipError_t launch_step_graph(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
     std::vector<const uint8_t*> ptrs(d_samples, d_samples + p->subs.size());
-    if (!p->exec || p->graph_T != n_time || p->graph_ptrs != ptrs) {
-        if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    epic_plan_s::GraphEntry* hit = nullptr;
+    for (auto& g : p->graphs)
+        if (g.T == n_time && g.ptrs == ptrs) hit = &g;
+    if (!hit) {
+        if (p->graphs.size() >= kGraphCache) {
+            auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                        [](const auto& x, const auto& y) { return x.last < y.last; });
+            (void)hipGraphExecDestroy(lru->exec);
+            (void)hipGraphDestroy(lru->graph);
+            p->graphs.erase(lru);
+        }
+        epic_plan_s::GraphEntry g{n_time, ptrs, nullptr, nullptr, 0};
         hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
         hipError_t le = launch_step(p, d_samples, n_time, p->cap_stream);
-        e = hipStreamEndCapture(p->cap_stream, &p->graph);
-        if (le != hipSuccess) return le;
-        if (e != hipSuccess) return e;
-        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return e;
-        p->graph_T = n_time;
-        p->graph_ptrs = ptrs;
+        e = hipStreamEndCapture(p->cap_stream, &g.graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            return le != hipSuccess ? le : e;
+        }
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g.graph);
+            return e;
+        }
+        p->graphs.push_back(g);
+        ++p->graph_builds;
+        hit = &p->graphs.back();
     }
-    return hipGraphLaunch(p->exec, st);
+    hit->last = ++p->graph_clock;
+    return hipGraphLaunch(hit->exec, st);
+}
+
+// Zero-lag sums about to pass the exact int32 range: fold them into the lag
+// accumulator first (outside any captured graph), then count the new call.
+hipError_t autocorr_guard(epic_plan_s* p, int64_t n_time, hipStream_t st) {
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        const SubDev& d = p->subs[k].dev;
+        if (!d.vaa) continue;
+        if (p->ac_pending[k] > 0 && p->ac_pending[k] + n_time > p->ac_limit) {
+            hipError_t e = launch_autocorr_fold(d, st);
+            if (e != hipSuccess) return e;
+            p->ac_pending[k] = 0;
+        }
+        p->ac_pending[k] += n_time;
+    }
+    return hipSuccess;
+}
+
+// Spectra after which the zero-lag sums are folded: every term is at most 128
+// in magnitude, so int32 sums stay exact below 2^24 spectra.  The environment
+// variable EPIC_AUTOCORR_FOLD_LIMIT can lower it (tests use it to fold often).
+int64_t autocorr_fold_limit() {
+    const int64_t full = (1LL << 24) - 1;
+    const char* env = std::getenv("EPIC_AUTOCORR_FOLD_LIMIT");
+    if (!env || !*env) return full;
+    char* end = nullptr;
+    const long long v = std::strtoll(env, &end, 10);
+    if (end == env || *end != '\0' || v < 1 || v > full) return full;
+    return (int64_t)v;
 }
 
 epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p) {
@@ -519,6 +695,8 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
     p->dry_run = (desc->flags & EPIC_F_DRY_RUN) ? 1 : 0;
     p->device = desc->device;
     p->subs.resize(desc->n_sub);
+    p->ac_pending.assign(desc->n_sub, 0);
+    p->ac_limit = autocorr_fold_limit();
     for (int k = 0; k < desc->n_sub; ++k) {
         SubHost& h = p->subs[k];
         h.desc = desc->sub[k];
@@ -539,7 +717,17 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         d.A = h.desc.n_ant; d.P = h.desc.n_pol; d.C = h.desc.n_chan; d.N = h.desc.grid_n;
         d.K = h.desc.kernel_k; d.NPP = (d.P == 2) ? 4 : 1; d.nibble_order = h.desc.nibble_order;
         d.wmode = weight_mode(h, desc->flags);
+        d.gridder = desc->gridder;
+        if (d.gridder == EPIC_GRID_AUTO) d.gridder = desc->precision == EPIC_FP8 ? EPIC_GRID_BLOCK_GEMM : EPIC_GRID_GATHER;
+        if (d.gridder != EPIC_GRID_GATHER) {
+            // real weights shared by both pols (or single pol) only
+            if (!(d.wmode == kWShared || (d.P == 1 && d.wmode == kWReal))) return EPIC_E_UNSUPPORTED;
+            epic_status bs = build_bgemm(h, d.gridder == EPIC_GRID_DENSE_GEMM);
+            if (bs != EPIC_OK) return bs;
+        }
     }
+    bool any_gemm = false;
+    for (const SubHost& h : p->subs) any_gemm = any_gemm || h.dev.gridder != EPIC_GRID_GATHER;
     if (!p->dry_run) {
         hipError_t e = hipSetDevice(p->device);
         if (e != hipSuccess) return EPIC_E_ARG;
@@ -551,7 +739,7 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         if ((e = scratch_address(p->device, &sp)) != hipSuccess) return hip_status(e);
     }
     for (SubHost& h : p->subs) h.dev.precision = desc->precision;
-    if (desc->precision == EPIC_FP16 && desc->n_sub > 1) {
+    if (desc->precision == EPIC_FP16 && desc->n_sub > 1 && !any_gemm) {
         // the single persistent launch exists when the sub-arrays share a kernel family
         std::vector<SubDev> devs;
         for (SubHost& h : p->subs) devs.push_back(h.dev);
@@ -570,8 +758,10 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
     for (size_t k = 0; k < p->subs.size(); ++k) {
         SubHost& h = p->subs[k];
         SubDev& d = h.dev;
-        hipError_t e = (d.precision == EPIC_FP32) ? fp32_configure(d, p->dry_run ? -1 : p->device, p->num_cu)
-                                                  : mfma_configure(d, p->dry_run ? -1 : p->device, p->num_cu);
+        const int dev_or_none = p->dry_run ? -1 : p->device;
+        hipError_t e = (d.precision == EPIC_FP32)          ? fp32_configure(d, dev_or_none, p->num_cu)
+                       : (d.gridder != EPIC_GRID_GATHER) ? bg_configure(d, dev_or_none, p->num_cu)
+                                                         : mfma_configure(d, dev_or_none, p->num_cu);
         if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
         if (e != hipSuccess) return hip_status(e);
         // slots for whichever form runs (unused ones stay zero)
@@ -586,7 +776,8 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         for (SubHost& h : p->subs) {
             const SubDev& d = h.dev;
             p->device_bytes += (int64_t)d.S * d.C * d.NPP * d.N * d.N * 4 + (int64_t)h.grp_ant.size() * (2 + 1 + 8 * d.P) +
-                               (int64_t)h.cells_desc.size() * 8 + (int64_t)d.C * d.A * d.P * d.K * d.K * 8;
+                               (int64_t)h.cells_desc.size() * 8 + (int64_t)d.C * d.A * d.P * d.K * d.K * 8 +
+                               (int64_t)h.bg_ents.size() * 512 * (d.precision == EPIC_FP8 ? 3 : 4);
         }
         return EPIC_OK;
     }
@@ -621,6 +812,21 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if ((s = hip_status(launch_dft_matrix(d, st))) != EPIC_OK) return s;
         }
         if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
+        if (d.gridder != EPIC_GRID_GATHER) {
+            if ((s = upload(p, &d.bg_chans, h.bg_chans, st)) != EPIC_OK) return s;
+            if ((s = upload(p, &d.bg_tiles, h.bg_tiles, st)) != EPIC_OK) return s;
+            if ((s = upload(p, &d.bg_cells, h.bg_cells, st)) != EPIC_OK) return s;
+            if ((s = upload(p, &d.bg_ents, h.bg_ents, st)) != EPIC_OK) return s;
+            if ((s = upload(p, &d.bg_perm, h.bg_perm, st)) != EPIC_OK) return s;
+            if ((s = upload(p, &d.bg_dst, h.bg_dst, st)) != EPIC_OK) return s;
+            d.bg_nterm = d.precision == EPIC_FP8 ? 3 : 2;
+            const size_t wbytes = h.bg_ents.size() * 512 * (d.precision == EPIC_FP8 ? 1 : 2) * d.bg_nterm;
+            if ((s = dalloc(p, &d.bg_w, wbytes)) != EPIC_OK) return s;
+            if ((s = dalloc(p, &d.bg_scale, (size_t)2)) != EPIC_OK) return s;
+            if ((s = hip_status(hipMemsetAsync(d.bg_w, 0, wbytes, st))) != EPIC_OK) return s;
+            if ((s = hip_status(hipMemsetAsync(d.bg_scale, 0, 2 * sizeof(float), st))) != EPIC_OK) return s;
+            if ((s = hip_status(launch_bg_weights(d, st))) != EPIC_OK) return s;
+        }
         if (desc->flags & EPIC_F_REMOVE_AUTOCORR) {
             const size_t nv = (size_t)d.C * d.A * (d.P == 2 ? 4 : 1);
             const size_t nl = (size_t)d.C * (2 * d.K - 1) * (2 * d.K - 1) * (d.P == 2 ? 3 : 1) * 2;
@@ -700,8 +906,11 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
         if (s != EPIC_OK) return s;
         if (desc->output == EPIC_OUT_STOKES && desc->sub[k].n_pol != 2) return EPIC_E_ARG;
     }
-    if (desc->precision == EPIC_FP8) return EPIC_E_UNSUPPORTED;
-    if (desc->gridder != EPIC_GRID_AUTO && desc->gridder != EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
+    // gridding on the matrix cores needs a matrix-core precision; FP8 exists
+    // only as the gridding product's operand type
+    const bool gemm = desc->gridder == EPIC_GRID_DENSE_GEMM || desc->gridder == EPIC_GRID_BLOCK_GEMM;
+    if (gemm && desc->precision == EPIC_FP32) return EPIC_E_UNSUPPORTED;
+    if (desc->precision == EPIC_FP8 && desc->gridder == EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
     epic_plan_s* p = new (std::nothrow) epic_plan_s();
     if (!p) return EPIC_E_NOMEM;
     epic_status s;
@@ -732,8 +941,10 @@ epic_status epic_grid_fft_accumulate(epic_plan_t p, const uint8_t* const* d_samp
         if (!d_samples[k]) return EPIC_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (hipSetDevice(p->device) != hipSuccess) return check_device(p, hipErrorInvalidDevice);
-    hipError_t e = (p->desc.flags & EPIC_F_GRAPH) ? launch_step_graph(p, d_samples, n_time, st)
-                                                  : launch_step(p, d_samples, n_time, st);
+    hipError_t e = autocorr_guard(p, n_time, st);
+    if (e == hipSuccess)
+        e = (p->desc.flags & EPIC_F_GRAPH) ? launch_step_graph(p, d_samples, n_time, st)
+                                           : launch_step(p, d_samples, n_time, st);
     return check_device(p, e);
 }
 
@@ -761,6 +972,7 @@ epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, v
     for (size_t k = 0; k < p->subs.size(); ++k) {
         hipError_t e = launch_readout(p->subs[k].dev, d_images[k], p->desc.output == EPIC_OUT_STOKES, reset != 0, st);
         if (e != hipSuccess) return check_device(p, e);
+        if (!p->ac_pending.empty()) p->ac_pending[k] = 0;   // the read-out folded them
     }
     return EPIC_OK;
 }
@@ -798,8 +1010,7 @@ epic_status epic_image_noalloc(epic_plan_t p, const uint8_t* const* d_samples, i
     e = launch_zero(base, (int64_t)need, st);
     for (size_t k = 0; k < run.size() && e == hipSuccess && n_time > 0; ++k) {
         const SubDev& d = run[k];
-        e = (d.precision == EPIC_FP32) ? launch_fp32(d, d_samples[k], n_time, st)
-                                       : launch_mfma(d, d_samples[k], n_time, st);
+        e = launch_one(d, d_samples[k], n_time, st);
     }
     for (size_t k = 0; k < run.size() && e == hipSuccess; ++k)
         e = launch_readout(run[k], d_images[k], p->desc.output == EPIC_OUT_STOKES, 0, st);
@@ -828,6 +1039,7 @@ epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, voi
     // the autocorrelations gathered so far belong to the old gains
     hipError_t e = launch_autocorr_fold(d, st);
     if (e != hipSuccess) return check_device(p, e);
+    if (!p->ac_pending.empty()) p->ac_pending[sub] = 0;
     if (!h_gains) {
         d.gains = nullptr;
     } else {
@@ -857,7 +1069,9 @@ epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, voi
         p->gain_ev_pending = 1;
         d.gains = d.gains_buf;
     }
-    return check_device(p, launch_entry_weights(d, st));
+    e = launch_entry_weights(d, st);
+    if (e == hipSuccess && d.gridder != EPIC_GRID_GATHER) e = launch_bg_weights(d, st);
+    return check_device(p, e);
 }
 
 epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
@@ -887,7 +1101,13 @@ epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
         info->weight[k] = p->weights[k];
         info->col_split[k] = p->subs[k].dev.KS;
         info->workgroups[k] = p->batched ? p->bdev[k].grid_wg : p->subs[k].dev.grid_wg;
+        info->grid_form[k] = p->subs[k].dev.precision == EPIC_FP32 ? EPIC_GRID_GATHER : p->subs[k].dev.gridder;
+        info->grid_step[k] = p->subs[k].dev.gridder != EPIC_GRID_GATHER ? p->subs[k].dev.bg_tb : 1;
+        info->autocorr_pending[k] = (int32_t)p->ac_pending[k];
+        info->grid_blocks[k] = (int64_t)p->subs[k].bg_ents.size();
     }
+    info->graph_builds = p->graph_builds;
+    info->autocorr_fold_limit = (int32_t)p->ac_limit;
     return EPIC_OK;
 }
 

@@ -33,6 +33,8 @@ EPIC_OUT_POL, EPIC_OUT_STOKES = 0, 1
 EPIC_F_GRAPH, EPIC_F_AUTOTUNE, EPIC_F_DRY_RUN, EPIC_F_REMOVE_AUTOCORR, EPIC_F_COMPLEX_WEIGHTS = 1, 2, 4, 8, 16
 EPIC_F_ONE_LAUNCH = 32
 PRECISIONS = {"fp32": EPIC_FP32, "fp16": EPIC_FP16, "fp8": EPIC_FP8}
+GRIDDERS = {"auto": EPIC_GRID_AUTO, "gather": EPIC_GRID_GATHER, "dense": EPIC_GRID_DENSE_GEMM,
+            "block": EPIC_GRID_BLOCK_GEMM}
 
 
 class EpicError(RuntimeError):
@@ -64,7 +66,10 @@ class epic_plan_info(ctypes.Structure):
                 ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("weight", ctypes.c_int32 * 16), ("col_split", ctypes.c_int32 * 16),
                 ("workgroups", ctypes.c_int32 * 16), ("can_batch", ctypes.c_int32),
-                ("form_ms", ctypes.c_double * 2)]
+                ("form_ms", ctypes.c_double * 2), ("grid_form", ctypes.c_int32 * 16),
+                ("grid_step", ctypes.c_int32 * 16), ("graph_builds", ctypes.c_int32),
+                ("autocorr_pending", ctypes.c_int32 * 16), ("autocorr_fold_limit", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int64 * 16)]
 
 
 _P = ctypes.POINTER
@@ -191,6 +196,8 @@ def epic_plan(subs: Sequence, precision=EPIC_FP32, gridder=EPIC_GRID_AUTO, outpu
     grid_dl, freq0_hz, dfreq_hz, kernel_k)."""
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
+    if isinstance(gridder, str):
+        gridder = GRIDDERS[gridder]
     n = len(subs)
     arr = (epic_array_desc * max(n, 1))()
     keep = []
@@ -288,7 +295,10 @@ def epic_plan_query(plan: Plan) -> dict:
             "lds_bytes": list(info.lds_bytes[:n]), "graph": info.graph, "autotuned": info.autotuned,
             "batched": info.batched, "weight": list(info.weight[:n]), "col_split": list(info.col_split[:n]),
             "workgroups": list(info.workgroups[:n]), "can_batch": info.can_batch,
-            "form_ms": list(info.form_ms)}
+            "form_ms": list(info.form_ms), "grid_form": list(info.grid_form[:n]),
+            "grid_step": list(info.grid_step[:n]), "graph_builds": info.graph_builds,
+            "autocorr_pending": list(info.autocorr_pending[:n]), "autocorr_fold_limit": info.autocorr_fold_limit,
+            "grid_blocks": list(info.grid_blocks[:n])}
 
 
 def epic_debug_schedule(plan: Plan, sub: int, n_time: int):

@@ -232,3 +232,23 @@ def test_plans_from_several_threads(E):
         t.join()
     assert not errors, errors[0]
     assert len(done) == 8 * 15
+
+
+def test_autocorr_fold_limit_setting(E, monkeypatch):
+    """The zero-lag sums fold before 2^24 - 1 spectra (int32-exact: every
+    term is at most 128); EPIC_AUTOCORR_FOLD_LIMIT lowers it, and values
+    outside [1, 2^24 - 1] or not a number keep the default."""
+    s = [Sub()]
+    for env, want in ((None, (1 << 24) - 1), ("7", 7), ("0", (1 << 24) - 1), ("abc", (1 << 24) - 1),
+                      (str(1 << 25), (1 << 24) - 1)):
+        if env is None:
+            monkeypatch.delenv("EPIC_AUTOCORR_FOLD_LIMIT", raising=False)
+        else:
+            monkeypatch.setenv("EPIC_AUTOCORR_FOLD_LIMIT", env)
+        p = dry(E, s, flags=E.EPIC_F_REMOVE_AUTOCORR)
+        try:
+            info = E.epic_plan_query(p)
+            assert info["autocorr_fold_limit"] == want, env
+            assert info["autocorr_pending"] == [0]
+        finally:
+            E.epic_destroy(p)

@@ -198,15 +198,15 @@ def test_real_gains_and_refusals(E):
 
 @pytest.mark.parametrize("flags", [0, 8])
 def test_stokes_output(E, flags):
-    """I = XX+YY, Q = XX-YY, U = 2 Re XY*, V = -2 Im XY* (linear feeds), also
+    """I = XX+YY, Q = XX-YY, U = 2 Re XY*, V = 2 Im XY* (linear feeds), also
     after autocorrelation removal."""
     sub = synth.shrink(synth.workload(2).subs[0], n_chan=2)
     x = synth.samples(sub, 12)
     (o,) = run_plan(E, [sub], [("acc", [x]), ("read", 1)], flags=flags, output=E.EPIC_OUT_STOKES)
     full = oracle.image(sub, x)
     pol = full - (oracle.autocorr(sub, x) if flags else 0.0)
-    st = np.stack([pol[:, 0] + pol[:, 1], pol[:, 0] - pol[:, 1], 2 * pol[:, 2], -2 * pol[:, 3]], axis=1)
-    fst = np.stack([full[:, 0] + full[:, 1], full[:, 0] - full[:, 1], 2 * full[:, 2], -2 * full[:, 3]], axis=1)
+    st = np.stack([pol[:, 0] + pol[:, 1], pol[:, 0] - pol[:, 1], 2 * pol[:, 2], 2 * pol[:, 3]], axis=1)
+    fst = np.stack([full[:, 0] + full[:, 1], full[:, 0] - full[:, 1], 2 * full[:, 2], 2 * full[:, 3]], axis=1)
     peak = np.abs(fst[:, 0]).max()
     assert np.abs(o[0] - st).max() <= 1e-5 * peak
 
@@ -318,7 +318,87 @@ def test_autocorr_removed_and_stokes_on_split_columns(E, precision, tol):
                     output=E.EPIC_OUT_STOKES)
     full = oracle.image(sub, x)
     pol = full - oracle.autocorr(sub, x)
-    st = np.stack([pol[:, 0] + pol[:, 1], pol[:, 0] - pol[:, 1], 2 * pol[:, 2], -2 * pol[:, 3]], axis=1)
-    fst = np.stack([full[:, 0] + full[:, 1], full[:, 0] - full[:, 1], 2 * full[:, 2], -2 * full[:, 3]], axis=1)
+    st = np.stack([pol[:, 0] + pol[:, 1], pol[:, 0] - pol[:, 1], 2 * pol[:, 2], 2 * pol[:, 3]], axis=1)
+    fst = np.stack([full[:, 0] + full[:, 1], full[:, 0] - full[:, 1], 2 * full[:, 2], 2 * full[:, 3]], axis=1)
     peak = np.abs(fst[:, 0]).max()
     assert np.abs(o[0] - st).max() <= tol * peak
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_stokes_v_sign_of_a_circular_source(E, sign):
+    """The sign of V is fixed by the voltages: a noise-free point source whose
+    Y field is E_Y = sign * i * E_X gives XY* = -sign i |E_X|^2, so
+    V = 2 Im XY* = -sign * I at its pixel (and Q = U = 0 there): V = +I for
+    E_Y = -i E_X.  The samples are exact 4-bit integers (amplitude 5)."""
+    torch, dev = torch_dev()
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=1)
+    N = sub.grid_n
+    i0, j0 = N // 2 + 7, N // 2 - 5
+    l0, m0 = sub.pixel_lm(i0, j0)
+    lam = 299792458.0 / sub.freq0_hz
+    u, v = sub.ant_xy[:, 0] / lam, sub.ant_xy[:, 1] / lam
+    rng = np.random.default_rng(40)
+    T = 6
+    s = rng.choice([1, -1, 1j, -1j], size=T)                          # source signal per spectrum
+    ph = np.exp(-2j * np.pi * (u * l0 + v * m0))                      # plane-wave phase, Eq. 1
+    ex = np.round((5 * s[:, None] * ph[None, :]).real) + 1j * np.round((5 * s[:, None] * ph[None, :]).imag)
+    ey = sign * 1j * ex                                               # exact: swaps and negates components
+    x = np.zeros((T, 1, sub.n_ant, 2), dtype=np.uint8)
+    x[:, 0, :, 0] = synth.pack44(ex.real, ex.imag)
+    x[:, 0, :, 1] = synth.pack44(ey.real, ey.imag)
+    (o,) = run_plan(E, [sub], [("acc", [x]), ("read", 1)], output=E.EPIC_OUT_STOKES)
+    I, Q, U, V = o[0][0]
+    assert np.unravel_index(np.argmax(I), I.shape) == (j0, i0)
+    assert abs(V[j0, i0] + sign * I[j0, i0]) <= 1e-5 * I[j0, i0]
+    assert abs(Q[j0, i0]) <= 1e-5 * I[j0, i0] and abs(U[j0, i0]) <= 1e-5 * I[j0, i0]
+
+
+def test_autocorr_folds_before_the_exact_range_ends(E, monkeypatch):
+    """With the fold count lowered to 7 spectra, calls of 5 fold the pending
+    zero-lag sums before adding to them once they would pass 7; the image is
+    unchanged (folding only moves exact sums into the lag accumulator)."""
+    monkeypatch.setenv("EPIC_AUTOCORR_FOLD_LIMIT", "7")
+    torch, dev = torch_dev()
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    x = synth.samples(sub, 15)
+    plan = E.epic_plan([sub], max_time=5, flags=E.EPIC_F_REMOVE_AUTOCORR)
+    try:
+        info = E.epic_plan_query(plan)
+        assert info["autocorr_fold_limit"] == 7
+        d = torch.from_numpy(x).to(dev)
+        pend = []
+        for k in range(3):
+            E.epic_grid_fft_accumulate(plan, [d[5 * k:5 * k + 5]], 5)
+            pend.append(E.epic_plan_query(plan)["autocorr_pending"][0])
+        assert pend == [5, 5, 5]
+        out = torch.empty((2, 4, 64, 64), device=dev)
+        E.epic_readout(plan, [out], 1)
+        assert E.epic_plan_query(plan)["autocorr_pending"][0] == 0
+        torch.cuda.synchronize()
+        full = oracle.image(sub, x)
+        ref = full - oracle.autocorr(sub, x)
+        fro, mx = removed_errors(out.double().cpu().numpy(), ref, full)
+        assert fro <= 1e-5 and mx <= 1e-5
+    finally:
+        E.epic_destroy(plan)
+
+
+def test_graph_cache_alternating_buffers(E):
+    """A caller rotating over two input buffers replays two captured graphs
+    instead of capturing on every call; every replay is right."""
+    torch, dev = torch_dev()
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    x = synth.samples(sub, 12)
+    bufs = [torch.from_numpy(x[:6].copy()).to(dev), torch.from_numpy(x[6:].copy()).to(dev)]
+    ref = [oracle.image(sub, x[:6]), oracle.image(sub, x[6:])]
+    plan = E.epic_plan([sub], max_time=6, flags=E.EPIC_F_GRAPH)
+    try:
+        out = torch.empty((2, 4, 64, 64), device=dev)
+        for k in range(6):
+            E.epic_grid_fft_accumulate(plan, [bufs[k % 2]], 6)
+            E.epic_readout(plan, [out], 1)
+            torch.cuda.synchronize()
+            assert_parity(out.double().cpu().numpy(), ref[k % 2], 1e-5, f"graph replay {k}")
+        assert E.epic_plan_query(plan)["graph_builds"] == 2
+    finally:
+        E.epic_destroy(plan)
