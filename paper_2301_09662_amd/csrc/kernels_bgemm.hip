@@ -87,9 +87,16 @@ struct BgArgs {
     int grid_wg, wg_per_xcd;
 };
 
+// Register budget: two waves per SIMD for the grids up to 64 with at most two
+// MFMA steps (their ~220 live registers fit without spilling: measured at the
+// station shape, 1.19 ms with three waves and ~60 spilled registers against
+// 0.80 ms with two); the compiler's choice otherwise.
+template <int N_, int KK_>
+constexpr int bg_waves_per_eu() { return (N_ <= 64 && KK_ <= 2) ? 2 : 1; }
+
 template <int N_, int KK_, int P, int OP>
 __global__ void __launch_bounds__(mfma_threads<N_>())
-__attribute__((amdgpu_waves_per_eu(MShape<N_, KK_>::WAVES_PER_EU))) bg_kernel(BgArgs a) {
+__attribute__((amdgpu_waves_per_eu(bg_waves_per_eu<N_, KK_>()))) bg_kernel(BgArgs a) {
     using Sh = MShape<N_, KK_>;
     using Op = typename Operand<OP>::type;
     constexpr int TH = mfma_threads<N_>(), NW = TH / 64;
@@ -183,55 +190,77 @@ __attribute__((amdgpu_waves_per_eu(MShape<N_, KK_>::WAVES_PER_EU))) bg_kernel(Bg
         for (int64_t u0 = 0; u0 < n; u0 += a.TB) {
             const int nb = (int)std::min<int64_t>(a.TB, n - u0);
             __builtin_amdgcn_s_setprio(2);
-            // 2. gridding product, tile by tile: G rows (cells) x columns (u, p, re/im)
-            for (int i = wave; i < bc.n_tile; i += NW) {
-                const uint2 td = a.tiles[bc.tile_off + i];
-                floatx4 dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
-                // block entries of the tile, each one's operands loaded while the
-                // previous one multiplies
-                const int cnt = (int)td.y;
-                const int ent0 = bc.ent_off + (int)td.x;
-                auto load = [&](int q, Op (&w)[NTERM], Op& eb) {
-                    const int ent = ent0 + q;
+            // 2. gridding product: G rows (cells) x columns (u, p, re/im), two
+            //    tiles of the wave at a time with the operands of two block
+            //    entries of each in flight, so that the weight loads from L2
+            //    overlap instead of queueing behind each other
+            for (int i0 = wave; i0 < bc.n_tile; i0 += 2 * NW) {
+                const int i1 = i0 + NW;
+                const uint2 t0 = a.tiles[bc.tile_off + i0];
+                const uint2 t1 = (i1 < bc.n_tile) ? a.tiles[bc.tile_off + i1] : make_uint2(0u, 0u);
+                const int n0 = (int)t0.y, n1 = (int)t1.y;
+                floatx4 d0[NTERM], d1[NTERM];
+#pragma unroll
+                for (int h = 0; h < NTERM; ++h) {
+                    d0[h] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    d1[h] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+                auto load = [&](int ent, Op (&w)[NTERM], Op& eb) {
                     const unsigned char* src = a.w + ((size_t)ent * 64 + lane) * 8 * EB;
 #pragma unroll
                     for (int h = 0; h < NTERM; ++h) w[h] = *reinterpret_cast<const Op*>(src + h * a.wterm);
                     eb = *reinterpret_cast<const Op*>(s_E + ((int)a.ents[ent] * 64 + lane) * 8 * EB);
                 };
-                floatx4 dm = {0.f, 0.f, 0.f, 0.f};
-                Op w[NTERM], eb;
-                if (cnt > 0) load(0, w, eb);
-                for (int q = 0; q < cnt; ++q) {
-                    Op nw[NTERM], ne = eb;
+                const int nmax = n0 > n1 ? n0 : n1;
+                for (int q0 = 0; q0 < nmax; q0 += 2) {
+                    Op w0[2][NTERM], e0[2], w1[2][NTERM], e1[2];
 #pragma unroll
-                    for (int h = 0; h < NTERM; ++h) nw[h] = w[h];
-                    if (q + 1 < cnt) load(q + 1, nw, ne);
-                    dh = mfma_op<OP>(w[0], eb, dh);
-                    if constexpr (OP == kBgFp16) {
-                        dh = mfma_op<OP>(w[1], eb, dh);
-                    } else {
-                        dm = mfma_op<OP>(w[1], eb, dm);
-                        dl = mfma_op<OP>(w[2], eb, dl);
+                    for (int q = 0; q < 2; ++q) {
+                        if (q0 + q < n0) load(bc.ent_off + (int)t0.x + q0 + q, w0[q], e0[q]);
+                        if (q0 + q < n1) load(bc.ent_off + (int)t1.x + q0 + q, w1[q], e1[q]);
                     }
 #pragma unroll
-                    for (int h = 0; h < NTERM; ++h) w[h] = nw[h];
-                    eb = ne;
+                    for (int q = 0; q < 2; ++q) {
+                        if (q0 + q < n0) {
+                            if constexpr (OP == kBgFp16) {
+                                d0[0] = mfma_op<OP>(w0[q][0], e0[q], d0[0]);
+                                d0[0] = mfma_op<OP>(w0[q][1], e0[q], d0[0]);
+                            } else {
+#pragma unroll
+                                for (int h = 0; h < NTERM; ++h) d0[h] = mfma_op<OP>(w0[q][h], e0[q], d0[h]);
+                            }
+                        }
+                        if (q0 + q < n1) {
+                            if constexpr (OP == kBgFp16) {
+                                d1[0] = mfma_op<OP>(w1[q][0], e1[q], d1[0]);
+                                d1[0] = mfma_op<OP>(w1[q][1], e1[q], d1[0]);
+                            } else {
+#pragma unroll
+                                for (int h = 0; h < NTERM; ++h) d1[h] = mfma_op<OP>(w1[q][h], e1[q], d1[h]);
+                            }
+                        }
+                    }
                 }
                 // D lane l: cells 4 (l / 16) + e of the tile, column l % 16
                 const int ucol = l16 / (2 * P);
                 if (ucol < nb) {
                     const int p = (P == 2) ? ((l16 >> 1) & 1) : 0;
                     const int ri = l16 & 1;
-                    const uint2 cw = *reinterpret_cast<const uint2*>(a.cells + ((size_t)bc.tile_off + i) * 16 + 4 * l4);
                     _Float16* dst = s_A1 + (ucol * M1 + p * R4) * A1P + ri * KPAD;
+                    auto store = [&](int i, const floatx4 (&d)[NTERM]) {
+                        const uint2 cw =
+                            *reinterpret_cast<const uint2*>(a.cells + ((size_t)bc.tile_off + i) * 16 + 4 * l4);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const uint32_t cv = ((e < 2) ? cw.x : cw.y) >> (16 * (e & 1)) & 0xFFFFu;
-                        float val = dh[e];
-                        if constexpr (OP == kBgFp8)
-                            val = fmaf(fmaf(dl[e], 0.0625f, dm[e]), 0.0625f, dh[e]) * inv_scale;
-                        if (cv != 0xFFFFu) dst[(int)(cv >> 8) * A1P + (int)(cv & 0xFFu)] = (_Float16)val;
-                    }
+                        for (int e = 0; e < 4; ++e) {
+                            const uint32_t cv = ((e < 2) ? cw.x : cw.y) >> (16 * (e & 1)) & 0xFFFFu;
+                            float val = d[0][e];
+                            if constexpr (OP == kBgFp8)
+                                val = fmaf(fmaf(d[2][e], 0.0625f, d[1][e]), 0.0625f, d[0][e]) * inv_scale;
+                            if (cv != 0xFFFFu) dst[(int)(cv >> 8) * A1P + (int)(cv & 0xFFu)] = (_Float16)val;
+                        }
+                    };
+                    store(i0, d0);
+                    if (i1 < bc.n_tile) store(i1, d1);
                 }
             }
             __syncthreads();
@@ -366,7 +395,8 @@ int op_of(const SubDev& d) { return d.precision == EPIC_FP8 ? kBgFp8 : kBgFp16; 
 // Launch shape of the GEMM-gridding form: the same grids and column split as
 // the gather form; TB spectra per gridding step, the most of 16 / (2 P),
 // 8 / (2 P), ... whose LDS lets the shape's target workgroups share a CU
-// (three for N <= 64 with at most two MFMA steps, else one).
+// (two for N <= 64 with at most two MFMA steps, as the registers allow, else
+// one).
 hipError_t bg_configure(SubDev& d, int device, int num_cu) {
     const int need = std::max(d.Rmax, d.Wmax);
     d.KK = (need + 15) / 16;
@@ -375,7 +405,7 @@ hipError_t bg_configure(SubDev& d, int device, int num_cu) {
     if (!(d.wmode == kWShared || (d.P == 1 && d.wmode == kWReal))) return hipErrorNotSupported;
     d.KS = d.N > 64 ? 2 : 1;
     d.threads = 64 * (d.N / 16);
-    const int target = (d.N <= 64 && d.KK <= 2) ? 3 : 1;
+    const int target = (d.N <= 64 && d.KK <= 2) ? 2 : 1;   // workgroups per CU the registers allow
     const int tbmax = 16 / (2 * d.P);
     int tb = 0;
     for (int cand = tbmax; cand >= 1 && tb == 0; cand /= 2)
