@@ -78,7 +78,15 @@ typedef enum {
 enum {
     EPIC_F_GRAPH = 1u,            /* replay accumulate steps from captured hipGraphs, one per
                                      (n_time, input pointers); the 4 most recent are kept */
-    EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time */
+    EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time: per FP16 sub-array
+                                     with EPIC_GRID_AUTO the gather form (gather program in LDS
+                                     or streamed from L2) against the block-GEMM form at every
+                                     step size that fits; for several FP16 sub-arrays, the cost
+                                     weights of the single launch and that launch against one
+                                     launch per sub-array.  If the environment variable
+                                     EPIC_TUNE_CACHE names a file, the choices are stored there
+                                     (a JSON object keyed by device architecture and plan shape)
+                                     and later plans of the same key reuse them untimed */
     EPIC_F_DRY_RUN = 4u,          /* validate and size on the CPU; touch no device */
     EPIC_F_REMOVE_AUTOCORR = 8u,  /* subtract each antenna's own power term (a = b) at read-out.
                                      Its zero-lag sums are exact int32 integers; an accumulate
@@ -154,7 +162,8 @@ typedef struct {
     int64_t device_bytes;          /* device memory owned by the plan */
     int64_t lds_bytes[16];         /* LDS per workgroup of each sub-array's kernel */
     int32_t graph;                 /* 1 if accumulate replays a hipGraph */
-    int32_t autotuned;             /* 1 if the work split came from timing */
+    int32_t autotuned;             /* 1: launch forms / work split timed at plan time;
+                                      2: taken from the EPIC_TUNE_CACHE file */
     int32_t batched;               /* 1 if all sub-arrays run in one launch */
     int32_t weight[16];            /* batched: cost of one spectrum per sub-array */
     int32_t col_split[16];         /* KS: workgroups sharing one spectrum's image columns */

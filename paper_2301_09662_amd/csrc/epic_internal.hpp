@@ -142,13 +142,15 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
                        float* efield = nullptr);
 
 // The FP16 matrix-core hot path (same contract as launch_fp32).
-hipError_t mfma_configure(SubDev& d, int device, int num_cu);
+// force_prog: -1 library choice, 0 / 1 gather program streamed from L2 / in LDS
+hipError_t mfma_configure(SubDev& d, int device, int num_cu, int force_prog = -1);
 hipError_t launch_dft_matrix(const SubDev& d, hipStream_t st);
 hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 
 // Gridding on the matrix cores (kernels_bgemm.hip): launch shape, the split
 // operand weights (after launch_entry_weights), and the hot path.
-hipError_t bg_configure(SubDev& d, int device, int num_cu);
+// force_tb: 0 library choice, else that many spectra per gridding step
+hipError_t bg_configure(SubDev& d, int device, int num_cu, int force_tb = 0);
 hipError_t launch_bg_weights(const SubDev& d, hipStream_t st);
 hipError_t launch_bgemm(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 

@@ -397,7 +397,7 @@ int op_of(const SubDev& d) { return d.precision == EPIC_FP8 ? kBgFp8 : kBgFp16; 
 // 8 / (2 P), ... whose LDS lets the shape's target workgroups share a CU
 // (two for N <= 64 with at most two MFMA steps, as the registers allow, else
 // one).
-hipError_t bg_configure(SubDev& d, int device, int num_cu) {
+hipError_t bg_configure(SubDev& d, int device, int num_cu, int force_tb) {
     const int need = std::max(d.Rmax, d.Wmax);
     d.KK = (need + 15) / 16;
     if (d.N < 32 || d.N > 128 || d.N % 16 != 0 || d.N == 80 || d.N == 112) return hipErrorNotSupported;
@@ -413,6 +413,10 @@ hipError_t bg_configure(SubDev& d, int device, int num_cu) {
     for (int cand = tbmax; cand >= 1 && tb == 0; cand /= 2)
         if (bg_layout(d, cand).total <= kLdsLimit) tb = cand;
     if (tb == 0) return hipErrorNotSupported;
+    if (force_tb > 0) {   // a candidate of the autotuner: any step size whose LDS fits
+        if (force_tb > tbmax || bg_layout(d, force_tb).total > kLdsLimit) return hipErrorNotSupported;
+        tb = force_tb;
+    }
     d.bg_tb = tb;
     const BgLayout L = bg_layout(d, tb);
     d.lds_bytes = L.total;

@@ -433,7 +433,7 @@ __global__ void dft_matrix_kernel(_Float16* __restrict__ m, int N, int KPAD) {
 
 }  // namespace
 
-hipError_t mfma_configure(SubDev& d, int device, int num_cu) {
+hipError_t mfma_configure(SubDev& d, int device, int num_cu, int force_prog) {
     const int need = std::max(d.Rmax, d.Wmax);
     d.KK = (need + 15) / 16;
     if (d.N < 32 || d.N > 128 || d.N % 16 != 0 || d.N == 80 || d.N == 112) return hipErrorNotSupported;
@@ -442,7 +442,7 @@ hipError_t mfma_configure(SubDev& d, int device, int num_cu) {
     d.threads = 64 * (d.N / 16);
     const Layout with = layout(d, true);
     const Layout without = layout(d, false);
-    const bool prog = prefer_prog(with.total, without.total);
+    const bool prog = force_prog < 0 ? prefer_prog(with.total, without.total) : force_prog != 0;
     const Layout& L = prog ? with : without;
     if (L.total > kLdsLimit) return hipErrorNotSupported;
     d.lds_bytes = L.total;

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <set>
+#include <string>
 #include <vector>
 
 #include "epic_gather.hpp"
@@ -76,6 +77,10 @@ struct SubHost {
     std::vector<uint16_t> bg_ents;
     std::vector<int32_t> bg_perm;
     std::vector<int32_t> bg_dst;
+    // autotuner candidates of this sub-array's launch (gridding form, gather
+    // program placement, spectra per gridding step); cands[0] the default
+    bool tune = false;
+    std::vector<SubDev> cands;
     SubDev dev{};
 };
 
@@ -100,7 +105,7 @@ struct epic_plan_s {
     BatchDev bd{};
     std::vector<int> weights;        // cost of one spectrum per sub-array
     std::vector<BatchSub> table;     // host copy of bd.table
-    int autotuned = 0;
+    int autotuned = 0;               // 1: timed at plan time, 2: taken from the tuning cache
     // hipGraph replay of accumulate steps: one executable graph per (spectra
     // count, input pointers), the kGraphCache most recently used kept
     hipStream_t cap_stream = nullptr;
@@ -676,6 +681,213 @@ hipError_t autocorr_guard(epic_plan_s* p, int64_t n_time, hipStream_t st) {
     return hipSuccess;
 }
 
+// ---- autotuner of the launch forms ------------------------------------------
+// Launch-shape settings of a candidate (its tables are the sub-array's own).
+void apply_config(SubDev& d, const SubDev& c) {
+    d.threads = c.threads;
+    d.lds_bytes = c.lds_bytes;
+    d.grid_wg = c.grid_wg;
+    d.prog_lds = c.prog_lds;
+    d.gridder = c.gridder;
+    d.bg_tb = c.bg_tb;
+    d.KS = c.KS;
+    d.KK = c.KK;
+}
+
+std::string cand_name(const SubDev& c) {
+    return "g" + std::to_string(c.gridder) + ",tb" + std::to_string(c.gridder == EPIC_GRID_GATHER ? 1 : c.bg_tb) +
+           ",prog" + std::to_string(c.prog_lds);
+}
+
+// Time every candidate of every sub-array with more than one, alone, on an
+// all-zero probe call (the work does not depend on the sample values) of
+// min(max_time, 64) spectra into scratch slots; keep the fastest (best of
+// three after a warm-up call).
+epic_status tune_forms(epic_plan_s* p, hipStream_t st) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return EPIC_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return EPIC_E_DEVICE; }
+    epic_status rc = EPIC_OK;
+    bool timed = false;
+    for (SubHost& h : p->subs) {
+        if (h.cands.size() < 2 || rc != EPIC_OK) continue;
+        const SubDev& d = h.dev;
+        const int64_t Tn = std::min<int64_t>(p->desc.max_time, 64);
+        int64_t S = 1;
+        for (const SubDev& c : h.cands) S = std::max<int64_t>(S, choose_slots(c, Tn));
+        uint8_t* in = nullptr;
+        float* slots = nullptr;
+        const size_t in_bytes = (size_t)Tn * d.C * d.A * d.P;
+        const size_t slot_bytes = (size_t)S * d.C * d.NPP * d.N * d.N * sizeof(float);
+        if (hipMalloc(&in, in_bytes) != hipSuccess || hipMalloc(&slots, slot_bytes) != hipSuccess) rc = EPIC_E_NOMEM;
+        if (rc == EPIC_OK && (hipMemsetAsync(in, 0, in_bytes, st) != hipSuccess ||
+                              hipMemsetAsync(slots, 0, slot_bytes, st) != hipSuccess))
+            rc = EPIC_E_DEVICE;
+        size_t best = 0;
+        double best_ms = 1e30;
+        for (size_t k = 0; k < h.cands.size() && rc == EPIC_OK; ++k) {
+            SubDev run = d;
+            apply_config(run, h.cands[k]);
+            run.slots = slots;
+            run.S = (int)S;
+            run.vaa = nullptr;
+            double ms_k = 1e30;
+            for (int rep = 0; rep < 4 && rc == EPIC_OK; ++rep) {
+                float ms = 0.f;
+                if (hipEventRecord(e0, st) != hipSuccess || launch_one(run, in, Tn, st) != hipSuccess ||
+                    hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = EPIC_E_DEVICE;
+                    break;
+                }
+                if (rep > 0) ms_k = std::min(ms_k, (double)ms);
+            }
+            if (ms_k < best_ms) {
+                best_ms = ms_k;
+                best = k;
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        if (slots) (void)hipFree(slots);
+        if (in) (void)hipFree(in);
+        if (rc == EPIC_OK) {
+            apply_config(h.dev, h.cands[best]);
+            timed = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == EPIC_OK && timed) p->autotuned = 1;
+    return rc;
+}
+
+// Tuning cache: a JSON object in the file named by EPIC_TUNE_CACHE, one entry
+// per line, "key": "value", the key naming the device architecture and the
+// plan's shapes, the value the choices (per sub-array candidate names; then
+// the launch form and cost weights of a multi-sub-array plan).
+std::string tune_key(const epic_plan_s* p) {
+    std::string k;
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) k += prop.gcnArchName;
+    k += "/cu" + std::to_string(p->num_cu) + "/prec" + std::to_string(p->desc.precision) + "/T" +
+         std::to_string(p->desc.max_time) + "/f" + std::to_string(p->desc.flags & (EPIC_F_ONE_LAUNCH | EPIC_F_GRAPH));
+    for (const SubHost& h : p->subs) {
+        const SubDev& d = h.dev;
+        k += "/A" + std::to_string(d.A) + "P" + std::to_string(d.P) + "C" + std::to_string(d.C) + "N" +
+             std::to_string(d.N) + "K" + std::to_string(d.K) + "w" + std::to_string(d.wmode) + "R" +
+             std::to_string(d.Rmax) + "W" + std::to_string(d.Wmax) + "G" + std::to_string(d.Gmax) + "c" +
+             std::to_string(d.CellMax) + "e" + std::to_string(h.bg_ents.size());
+    }
+    return k;
+}
+
+std::vector<std::pair<std::string, std::string>> tune_cache_read(const char* path) {
+    std::vector<std::pair<std::string, std::string>> out;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        // a line "key": "value"[,]
+        std::string s(line);
+        const size_t a = s.find('"'), b = s.find("\": \"", a + 1);
+        if (a == std::string::npos || b == std::string::npos) continue;
+        const size_t c = s.find('"', b + 4);
+        if (c == std::string::npos) continue;
+        out.emplace_back(s.substr(a + 1, b - a - 1), s.substr(b + 4, c - b - 4));
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool tune_cache_get(const std::string& key, std::string* val) {
+    const char* path = std::getenv("EPIC_TUNE_CACHE");
+    if (!path || !*path) return false;
+    for (const auto& kv : tune_cache_read(path))
+        if (kv.first == key) {
+            *val = kv.second;
+            return true;
+        }
+    return false;
+}
+
+void tune_cache_put(const std::string& key, const std::string& val) {
+    const char* path = std::getenv("EPIC_TUNE_CACHE");
+    if (!path || !*path) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    auto all = tune_cache_read(path);
+    bool found = false;
+    for (auto& kv : all)
+        if (kv.first == key) { kv.second = val; found = true; }
+    if (!found) all.emplace_back(key, val);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    for (size_t k = 0; k < all.size(); ++k)
+        std::fprintf(f, "\"%s\": \"%s\"%s\n", all[k].first.c_str(), all[k].second.c_str(), k + 1 < all.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    (void)std::rename(tmp.c_str(), path);
+}
+
+// "<sub 0 choice>;<sub 1 choice>...|batched|w0,w1,..."
+std::string tuned_value(const epic_plan_s* p) {
+    std::string v;
+    for (size_t k = 0; k < p->subs.size(); ++k) v += (k ? ";" : "") + cand_name(p->subs[k].dev);
+    v += "|" + std::to_string(p->batched) + "|";
+    for (size_t k = 0; k < p->weights.size(); ++k) v += (k ? "," : "") + std::to_string(p->weights[k]);
+    return v;
+}
+
+// Apply the per-sub-array choices of a cache entry; false (nothing changed)
+// unless every choice names one of the sub-array's candidates.
+bool apply_cached_forms(epic_plan_s* p, const std::string& val) {
+    const std::string forms = val.substr(0, val.find('|'));
+    std::vector<std::string> names;
+    size_t a = 0;
+    while (a <= forms.size()) {
+        const size_t b = forms.find(';', a);
+        names.push_back(forms.substr(a, b == std::string::npos ? std::string::npos : b - a));
+        if (b == std::string::npos) break;
+        a = b + 1;
+    }
+    if (names.size() != p->subs.size()) return false;
+    std::vector<const SubDev*> pick(p->subs.size(), nullptr);
+    for (size_t k = 0; k < p->subs.size(); ++k) {
+        const SubHost& h = p->subs[k];
+        if (h.cands.empty()) {
+            if (names[k] != cand_name(h.dev)) return false;
+            continue;
+        }
+        for (const SubDev& c : h.cands)
+            if (cand_name(c) == names[k]) pick[k] = &c;
+        if (!pick[k]) return false;
+    }
+    for (size_t k = 0; k < p->subs.size(); ++k)
+        if (pick[k]) apply_config(p->subs[k].dev, *pick[k]);
+    return true;
+}
+
+// The launch form and cost weights of a cache entry (multi-sub-array plans).
+epic_status apply_cached_batch(epic_plan_s* p, const std::string& val, hipStream_t st) {
+    const size_t a = val.find('|');
+    const size_t b = a == std::string::npos ? a : val.find('|', a + 1);
+    if (b == std::string::npos) return EPIC_OK;
+    p->batched = std::atoi(val.substr(a + 1, b - a - 1).c_str()) != 0 ? 1 : 0;
+    size_t k = 0, c = b + 1;
+    while (c < val.size() && k < p->weights.size()) {
+        p->weights[k] = std::max(1, std::atoi(val.c_str() + c));
+        p->table[k].weight = p->weights[k];
+        const size_t n = val.find(',', c);
+        if (n == std::string::npos) break;
+        c = n + 1;
+        ++k;
+    }
+    return hip_status(hipMemcpyAsync(p->bd.table, p->table.data(), p->table.size() * sizeof(BatchSub),
+                                     hipMemcpyHostToDevice, st));
+}
+
 // Spectra after which the zero-lag sums are folded: every term is at most 128
 // in magnitude, so int32 sums stay exact below 2^24 spectra.  The environment
 // variable EPIC_AUTOCORR_FOLD_LIMIT can lower it (tests use it to fold often).
@@ -719,6 +931,15 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         d.wmode = weight_mode(h, desc->flags);
         d.gridder = desc->gridder;
         if (d.gridder == EPIC_GRID_AUTO) d.gridder = desc->precision == EPIC_FP8 ? EPIC_GRID_BLOCK_GEMM : EPIC_GRID_GATHER;
+        // with EPIC_F_AUTOTUNE and the library's choice of gridder, FP16 arrays
+        // whose weights the matrix-core product takes are timed both ways
+        h.tune = desc->gridder == EPIC_GRID_AUTO && desc->precision == EPIC_FP16 && (desc->flags & EPIC_F_AUTOTUNE) &&
+                 !(desc->flags & EPIC_F_ONE_LAUNCH) && (d.wmode == kWShared || (d.P == 1 && d.wmode == kWReal));
+        if (h.tune) {
+            epic_status bs = build_bgemm(h, false);
+            if (bs == EPIC_E_UNSUPPORTED) h.tune = false;
+            else if (bs != EPIC_OK) return bs;
+        }
         if (d.gridder != EPIC_GRID_GATHER) {
             // real weights shared by both pols (or single pol) only
             if (!(d.wmode == kWShared || (d.P == 1 && d.wmode == kWReal))) return EPIC_E_UNSUPPORTED;
@@ -764,9 +985,22 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
                                                          : mfma_configure(d, dev_or_none, p->num_cu);
         if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
         if (e != hipSuccess) return hip_status(e);
+        // autotuner candidates: the other placement of the gather program, and
+        // the block-GEMM form at each step size whose LDS fits
+        if (h.tune) {
+            h.cands.assign(1, d);
+            SubDev alt = d;
+            if (mfma_configure(alt, dev_or_none, p->num_cu, d.prog_lds ? 0 : 1) == hipSuccess) h.cands.push_back(alt);
+            for (int tb = 16 / (2 * d.P); tb >= 1; tb /= 2) {
+                SubDev b = d;
+                b.gridder = EPIC_GRID_BLOCK_GEMM;
+                if (bg_configure(b, dev_or_none, p->num_cu, tb) == hipSuccess) h.cands.push_back(b);
+            }
+        }
         // slots for whichever form runs (unused ones stay zero)
         d.S = choose_slots(d, desc->max_time);
         if (p->can_batch) d.S = std::max(d.S, choose_slots(p->bdev[k], desc->max_time));
+        for (const SubDev& c : h.cands) d.S = std::max(d.S, choose_slots(c, desc->max_time));
         p->weights.push_back(p->can_batch ? model_weight(h) : 1);
         // size checks (also in dry run)
         const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
@@ -812,7 +1046,7 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if ((s = hip_status(launch_dft_matrix(d, st))) != EPIC_OK) return s;
         }
         if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
-        if (d.gridder != EPIC_GRID_GATHER) {
+        if (d.gridder != EPIC_GRID_GATHER || h.tune) {
             if ((s = upload(p, &d.bg_chans, h.bg_chans, st)) != EPIC_OK) return s;
             if ((s = upload(p, &d.bg_tiles, h.bg_tiles, st)) != EPIC_OK) return s;
             if ((s = upload(p, &d.bg_cells, h.bg_cells, st)) != EPIC_OK) return s;
@@ -836,6 +1070,21 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if ((s = hip_status(hipMemsetAsync(d.lag, 0, nl * sizeof(float), st))) != EPIC_OK) return s;
         }
     }
+    // autotuner: each sub-array's launch candidates timed (or their choice taken
+    // from the tuning cache); the single launch of several sub-arrays exists
+    // only while every one of them runs the gather form
+    std::string tune_key_str, cached;
+    bool cache_hit = false;
+    if (desc->flags & EPIC_F_AUTOTUNE) {
+        tune_key_str = tune_key(p);
+        cache_hit = tune_cache_get(tune_key_str, &cached) && apply_cached_forms(p, cached);
+        if (!cache_hit) {
+            epic_status s = tune_forms(p, st);
+            if (s != EPIC_OK) return s;
+        }
+    }
+    for (const SubHost& h : p->subs)
+        if (h.dev.gridder != EPIC_GRID_GATHER && p->can_batch) p->can_batch = p->batched = 0;
     if (p->can_batch) {
         // the batched form shares every table and buffer of the dedicated one
         for (size_t k = 0; k < p->subs.size(); ++k) p->bdev[k] = batch_view(p->subs[k].dev, p->bdev[k]);
@@ -847,9 +1096,15 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
                                            hipMemcpyHostToDevice, st))) != EPIC_OK)
             return s;
         if (desc->flags & EPIC_F_AUTOTUNE) {
-            if ((s = autotune_batch(p, st, (desc->flags & EPIC_F_ONE_LAUNCH) == 0)) != EPIC_OK) return s;
+            if (cache_hit) {
+                if ((s = apply_cached_batch(p, cached, st)) != EPIC_OK) return s;
+            } else if ((s = autotune_batch(p, st, (desc->flags & EPIC_F_ONE_LAUNCH) == 0)) != EPIC_OK) {
+                return s;
+            }
         }
     }
+    if ((desc->flags & EPIC_F_AUTOTUNE) && !cache_hit) tune_cache_put(tune_key_str, tuned_value(p));
+    if (cache_hit) p->autotuned = 2;
     if (desc->flags & EPIC_F_GRAPH) {
         hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_status(e);
