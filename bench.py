@@ -111,7 +111,7 @@ def mfma_ops_per_spectrum(plan, subs):
         ext = max(-(-int(R.max()) // 8) * 8, -(-int(W.max()) // 8) * 8)
         KK = -(-ext // 16)
         N, P = s.grid_n, s.n_pol
-        KS = 2 if N > 64 else 1
+        KS = 1 if N <= 64 else (2 if N <= 128 else (4 if N <= 192 else 8))
         NK = N // KS
         M1 = P * ((R + 3) // 4 * 4)
         per_c = KS * (-(-M1 // 16) * (2 * NK // 16) * KK + (N // 16) * (NK // 16) * P * 2 * KK)

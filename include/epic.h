@@ -121,8 +121,10 @@ typedef struct {
     int32_t n_chan;              /* C >= 1 */
     int32_t grid_n;              /* N: multiple of 16 in [16, 256].  Kernels exist
                                     for FP32 at 16..128 (every multiple of 16),
-                                    192 and 256; for FP16 at 32, 48, 64, 96 and
-                                    128.  Other sizes: EPIC_E_UNSUPPORTED */
+                                    192 and 256; for FP16 with gather gridding
+                                    at 32, 48, 64, 96, 128, 192 and 256; for
+                                    the GEMM gridders at 32..128 of those.
+                                    Other sizes: EPIC_E_UNSUPPORTED */
     int32_t kernel_k;            /* K: odd, 1..7 */
     int32_t nibble_order;        /* 0: real part in the high nibble; 1: swapped */
     double grid_dl;              /* grid spacing in wavelengths (> 0) */

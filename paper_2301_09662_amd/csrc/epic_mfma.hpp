@@ -34,11 +34,17 @@ struct MShape {
     static constexpr int KK = KK_;                 // 32-deep MFMA steps per product
     static constexpr int KPAD = 16 * KK;           // window extent padded (cells)
     static constexpr int K2 = 2 * KPAD;            // real-form depth: [re | im]
-    static constexpr int KS = (N > 64) ? 2 : 1;    // image columns split over KS workgroups
+    // image columns split over KS workgroups: a wave keeps its 16 image rows'
+    // products of NK columns in registers, at most 64 columns, and 32 for the
+    // 16-wave workgroups of N = 256 (whose 128-register budget holds no more)
+    static constexpr int KS = (N <= 64) ? 1 : (N <= 128 ? 2 : (N <= 192 ? 4 : 8));
     static constexpr int NK = N / KS;              // columns per workgroup
     static constexpr int IT = NK / 16;             // 16-column tiles per workgroup
     static constexpr int WAVES = N / 16;           // one wave per 16 image rows
-    static constexpr int NT1 = 2 / KS;             // row-pass output tiles per wave
+    static constexpr int TILES1 = 2 * NK / 16;     // row-pass output tiles: [Re | Im] of NK columns
+    static constexpr int NT1 = (TILES1 + WAVES - 1) / WAVES;   // row-pass output tiles per wave
+    // waves beyond TILES1 / NT1 (grids above 128) sit the row pass out
+    static constexpr bool ALL_ROW_WAVES = TILES1 == WAVES * NT1;
     // register budget: three waves per SIMD (168 VGPRs) for the small shapes,
     // where the extra resident workgroup outweighs a few spills (measured:
     // station N = 64, KK = 2: 0.75 -> 0.64 ms); the compiler's choice otherwise
@@ -74,6 +80,7 @@ __device__ __forceinline__ void load_row_fragments(half8 (&b1)[Sh::NT1][Sh::KK],
                                                    int kpart, int mw, int l16, int l4) {
 #pragma unroll
     for (int u = 0; u < Sh::NT1; ++u) {
+        if (!Sh::ALL_ROW_WAVES && mw * Sh::NT1 + u >= Sh::TILES1) continue;
         const int nloc = 16 * (mw * Sh::NT1 + u) + l16;          // own-column index in [0, 2 NK)
         const int row = (nloc < Sh::NK) ? kpart * Sh::NK + nloc : Sh::N + kpart * Sh::NK + (nloc - Sh::NK);
 #pragma unroll
@@ -101,6 +108,7 @@ __device__ __forceinline__ void row_pass(const _Float16* __restrict__ s_A1, _Flo
         const int m0 = 16 * mt + 4 * l4;
 #pragma unroll
         for (int u = 0; u < NT1; ++u) {
+            if (!Sh::ALL_ROW_WAVES && mw * NT1 + u >= Sh::TILES1) continue;
             floatx4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KK; ++ks) d = mfma16(af[ks], b1[u][ks], d);

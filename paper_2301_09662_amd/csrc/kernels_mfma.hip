@@ -335,7 +335,7 @@ struct Layout {
     int M1max;
 };
 
-int ks_of(int N) { return N > 64 ? 2 : 1; }
+int ks_of(int N) { return N <= 64 ? 1 : (N <= 128 ? 2 : (N <= 192 ? 4 : 8)); }
 
 size_t take_aligned(size_t& b, size_t n) {
     b = (b + 15) & ~(size_t)15;
@@ -375,7 +375,8 @@ KernelFn pick2(int P, int wm) {
     return wm == kWComplex ? mfma_kernel<N, KK, 1, kWComplex> : mfma_kernel<N, KK, 1, kWReal>;
 }
 
-// Grid sizes 32..128 (multiples of 16, not 80 / 112) with window depth KK*16 <= min(N, 64).
+// Grid sizes 32..128 (multiples of 16, not 80 / 112), 192 and 256, with
+// window depth KK*16 <= min(N, 64).
 KernelFn select_kernel(int N, int KK, int P, int wm) {
     switch (N * 8 + KK) {
 #define EPIC_K(NN, KKK) case NN * 8 + KKK: return pick2<NN, KKK>(P, wm);
@@ -384,6 +385,8 @@ KernelFn select_kernel(int N, int KK, int P, int wm) {
         EPIC_K(64, 1) EPIC_K(64, 2) EPIC_K(64, 3) EPIC_K(64, 4)
         EPIC_K(96, 1) EPIC_K(96, 2) EPIC_K(96, 3) EPIC_K(96, 4)
         EPIC_K(128, 1) EPIC_K(128, 2) EPIC_K(128, 3) EPIC_K(128, 4)
+        EPIC_K(192, 1) EPIC_K(192, 2) EPIC_K(192, 3) EPIC_K(192, 4)
+        EPIC_K(256, 1) EPIC_K(256, 2) EPIC_K(256, 3) EPIC_K(256, 4)
 #undef EPIC_K
     }
     return nullptr;
@@ -436,7 +439,9 @@ __global__ void dft_matrix_kernel(_Float16* __restrict__ m, int N, int KPAD) {
 hipError_t mfma_configure(SubDev& d, int device, int num_cu, int force_prog) {
     const int need = std::max(d.Rmax, d.Wmax);
     d.KK = (need + 15) / 16;
-    if (d.N < 32 || d.N > 128 || d.N % 16 != 0 || d.N == 80 || d.N == 112) return hipErrorNotSupported;
+    const bool grid_ok = (d.N >= 32 && d.N <= 128 && d.N % 16 == 0 && d.N != 80 && d.N != 112) || d.N == 192 ||
+                         d.N == 256;
+    if (!grid_ok) return hipErrorNotSupported;
     if (d.KK < 1 || 16 * d.KK > d.N || d.KK > 4) return hipErrorNotSupported;
     d.KS = ks_of(d.N);
     d.threads = 64 * (d.N / 16);
@@ -576,7 +581,7 @@ BatchSub batch_entry(const SubDev& d, int weight) {
     b.slots = d.slots;
     b.C = d.C; b.A = d.A; b.V = d.C * d.KS;
     b.N = d.N; b.KK = d.KK; b.KS = d.KS; b.NK = d.N / d.KS; b.IT = b.NK / 16; b.WAVES = d.N / 16;
-    b.NT1 = 2 / d.KS; b.WP = d.WP; b.M1max = m1max_of(d);
+    b.NT1 = (2 * b.NK / 16 + b.WAVES - 1) / b.WAVES; b.WP = d.WP; b.M1max = m1max_of(d);
     b.nibble_order = d.nibble_order; b.S = d.S; b.weight = weight; b.prog_lds = d.prog_lds;
     return b;
 }

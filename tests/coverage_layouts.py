@@ -103,7 +103,12 @@ MFMA_SHAPES = [(32, 1, 13, 9), (32, 2, 20, 29),
                (48, 1, 16, 12), (48, 2, 25, 31), (48, 3, 45, 40),
                (64, 1, 11, 14), (64, 2, 30, 18), (64, 3, 35, 44), (64, 4, 61, 50),
                (96, 1, 15, 10), (96, 2, 24, 32), (96, 3, 47, 33), (96, 4, 52, 63),
-               (128, 1, 9, 16), (128, 2, 32, 30), (128, 3, 41, 48), (128, 4, 64, 57)]
+               (128, 1, 9, 16), (128, 2, 32, 30), (128, 3, 41, 48), (128, 4, 64, 57),
+               (192, 1, 12, 15), (192, 2, 30, 20), (192, 3, 40, 45), (192, 4, 60, 55),
+               (256, 1, 16, 10), (256, 2, 25, 32), (256, 3, 44, 37), (256, 4, 58, 63)]
+
+# the shapes of the GEMM-gridding kernel (grids up to 128)
+BGEMM_SHAPES = [s for s in MFMA_SHAPES if s[0] <= 128]
 
 # the shapes the single persistent launch of several sub-arrays can run
 BATCH_SHAPES = [s for s in MFMA_SHAPES if s[0] <= 96]

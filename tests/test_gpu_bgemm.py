@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from coverage_layouts import MFMA_SHAPES, box, kk_of
+from coverage_layouts import BGEMM_SHAPES, box, kk_of
 from gpu_util import assert_parity, check_invariants, image_errors, oracle_channels, run_library
 
 TOL = 1e-3
@@ -109,7 +109,7 @@ def test_other_shapes(E, prec, cfg, k, nchan, T):
 def test_every_kernel_shape(E, part, prec):
     """Every (N, KK) instantiation of the GEMM-gridding kernel, dual pol, and
     four single-pol ones."""
-    shapes = [s for s in MFMA_SHAPES if (s[0] > 64) == bool(part)]
+    shapes = [s for s in BGEMM_SHAPES if (s[0] > 64) == bool(part)]
     subs = [box(N, W, R, P=1 if k % 4 == 3 else 2, seed=300 + 40 * part + k) for k, (N, KK, W, R) in enumerate(shapes)]
     xs = [np.random.default_rng(500 + k).integers(0, 256, (6, 1, s.n_ant, s.n_pol), dtype=np.uint8)
           for k, s in enumerate(subs)]

@@ -80,7 +80,7 @@ def test_mfma_layouts_reach_every_shape(E):
         finally:
             E.epic_destroy(plan)
     assert got == {(N, KK) for N, KK, _, _ in MFMA_SHAPES}
-    assert len(got) == 17
+    assert len(got) == 25
 
 
 def test_batch_layouts_reach_every_shape(E):
@@ -111,9 +111,9 @@ def test_fp32_every_fold(E, N):
 @pytest.mark.gpu
 @pytest.mark.parametrize("part", [0, 1])
 def test_fp16_every_mfma_shape(E, part):
-    """Every (N, KK) matrix-core kernel, one single-channel array each; the
-    N <= 64 half also runs the real-per-pol and complex weight modes and a
-    single-pol array."""
+    """Every (N, KK) matrix-core kernel (N = 32 .. 256), one single-channel
+    array each; the N <= 64 half also runs the real-per-pol and complex
+    weight modes and a single-pol array."""
     shapes = [s for s in MFMA_SHAPES if (s[0] > 64) == bool(part)]
     subs = mfma_subs(shapes, seed=40 * part)
     taps = [None] * len(subs)

@@ -113,3 +113,28 @@ def test_single_pol_split_columns(E):
     (gpu,), info = run_library(E, [sub], [x], precision="fp16")
     assert info["col_split"][0] == 2 and info["npp"][0] == 1
     assert_parity(gpu, oracle.image(sub, x), TOL, "fp16 single pol N=128")
+
+
+@pytest.mark.parametrize("n,dl,nchan,T,ks", [(256, 0.5, 2, 3, 8), (192, 0.5, 1, 4, 4)])
+def test_wide_grids(E, n, dl, nchan, T, ks):
+    """256 x 256 (image columns over eight workgroups, 16 row waves each) and
+    192 x 192 (four) in the FP16 form, station layout at half-wavelength cells."""
+    import dataclasses
+    sub = dataclasses.replace(synth.shrink(synth.workload(2).subs[0], n_chan=nchan), grid_n=n, grid_dl=dl)
+    x = synth.samples(sub, T)
+    (gpu,), info = run_library(E, [sub], [x], precision="fp16")
+    assert info["col_split"][0] == ks and info["threads"][0] == 64 * n // 16
+    fro, mx = assert_parity(gpu, oracle.image(sub, x), TOL, f"fp16 N={n}")
+    print(f"fp16 N={n}: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+
+
+def test_full_wide_grid_sampled_channel(E):
+    """The station on a 256 x 256 grid at half-wavelength cells (132 channels,
+    100 spectra in one call) in the FP16 form, against the oracle on its
+    highest channel (the largest window); invariants on all channels."""
+    sub, x, ora = oracle_channels(6, 100, (131,))
+    (gpu,), info = run_library(E, [sub], [x], precision="fp16")
+    assert info["col_split"][0] == 8
+    fro, mx = assert_parity(gpu[131:132], ora[131:132], TOL, "fp16 256 grid full, channel 131")
+    print(f"fp16 256 grid full, channel 131: rel err {fro:.2e}, max |d|/peak {mx:.2e}")
+    check_invariants(gpu)

@@ -140,7 +140,7 @@ def test_wide_grid_split(E, n, dl, ks):
 
 def test_grid_sizes_without_a_kernel(E):
     base = synth.shrink(synth.workload(2).subs[0], n_chan=1)
-    for n, prec in ((240, "fp32"), (256, "fp16"), (80, "fp16")):
+    for n, prec in ((240, "fp32"), (224, "fp16"), (80, "fp16")):
         with pytest.raises(E.EpicError) as ei:
             dry(E, [wide_grid(base, n, 0.5)], prec, 4)
         assert ei.value.status == E.EPIC_E_UNSUPPORTED, (n, prec)
