@@ -64,9 +64,16 @@ typedef enum {
     EPIC_GRID_DENSE_GEMM = 2,  /* kernel matrix [window cells x antennas] times the fields
                                   [antennas x (spectrum, pol, re/im)] on the matrix cores,
                                   every (16-cell tile, 32-antenna block) multiplied */
-    EPIC_GRID_BLOCK_GEMM = 3   /* the same product over the non-zero blocks only.  Both GEMM
+    EPIC_GRID_BLOCK_GEMM = 3,  /* the same product over the non-zero blocks only.  Both GEMM
                                   forms: FP16 / FP8 plans, real weights equal for both pols
                                   (else EPIC_E_UNSUPPORTED), one launch per sub-array */
+    EPIC_GRID_DIRECT_GEMM = 4  /* no aperture grid and no FFT: gridding and the transform
+                                  folded into one matrix per channel, each pixel's field the
+                                  product of the antennas' kernel images with their fields
+                                  (O(A N^2) per spectrum against O(N^2 log N), Sec. 1), FP16
+                                  hi + lo on the matrix cores.  FP16 plans, at most 64
+                                  antennas, grids up to 64, X and Y weights equal (else
+                                  EPIC_E_UNSUPPORTED); one launch per sub-array */
 } epic_gridder;
 
 /* Output products per pixel. */
@@ -173,7 +180,8 @@ typedef struct {
     int32_t can_batch;             /* 1 if the one-launch form exists for these sub-arrays */
     double form_ms[2];             /* autotuner: probe call time, one launch / one per sub-array */
     int32_t grid_form[16];         /* epic_gridder each sub-array's kernel runs */
-    int32_t grid_step[16];         /* spectra per gridding product (1 for the gather) */
+    int32_t grid_step[16];         /* spectra per gridding product (1 for the gather, 16 / n_pol
+                                      for the direct form) */
     int32_t graph_builds;          /* EPIC_F_GRAPH: graphs captured so far */
     int32_t autocorr_pending[16];  /* EPIC_F_REMOVE_AUTOCORR: spectra in the zero-lag sums
                                       since their last fold */

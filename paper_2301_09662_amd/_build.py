@@ -25,6 +25,7 @@ SOURCES = [
     # MFMA results in VGPRs: the products read them directly (no AGPR copies)
     ("kernels_mfma.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form"]),
     ("kernels_bgemm.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form"]),
+    ("kernels_direct.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form"]),
     ("kernels_aux.hip", []),
     ("plan.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

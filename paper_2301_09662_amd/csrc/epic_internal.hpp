@@ -104,6 +104,9 @@ struct SubDev {
     unsigned char* bg_w = nullptr;    // [terms][entries][64 lanes][8] split weights, high part first
     int bg_nterm = 2;                 // terms of the split (FP16: 2, FP8: 3)
     float* bg_scale = nullptr;        // [2] FP8 weight scale and its inverse
+    // direct imaging (EPIC_GRID_DIRECT_GEMM): per-channel kernel-image matrix
+    void* dir_m = nullptr;            // [C][N^2 / 8][A / 16][2 terms][64 lanes][8] FP16
+    int dir_chunks = 1;               // time chunks (partial accumulator slots) of a launch
 };
 
 // One sub-array as seen by the batched (several sub-arrays in one launch)
@@ -153,6 +156,13 @@ hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, 
 hipError_t bg_configure(SubDev& d, int device, int num_cu, int force_tb = 0);
 hipError_t launch_bg_weights(const SubDev& d, hipStream_t st);
 hipError_t launch_bgemm(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
+
+// Direct imaging on the matrix cores (kernels_direct.hip): launch shape,
+// the kernel-image matrix (FP64, split FP16 hi + lo), and the hot path.
+hipError_t direct_configure(SubDev& d, int num_cu, int64_t max_time);
+int64_t direct_matrix_halfs(const SubDev& d);
+hipError_t launch_direct_matrix(const SubDev& d, hipStream_t st);
+hipError_t launch_direct(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 
 // Several FP16 sub-arrays in one persistent launch.
 hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, int num_cu);

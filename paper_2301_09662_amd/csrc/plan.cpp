@@ -597,6 +597,7 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
 // The hot kernel of one sub-array in its own launch.
 hipError_t launch_one(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st) {
     if (d.precision == EPIC_FP32) return launch_fp32(d, samples, n_time, st);
+    if (d.gridder == EPIC_GRID_DIRECT_GEMM) return launch_direct(d, samples, n_time, st);
     if (d.gridder != EPIC_GRID_GATHER) return launch_bgemm(d, samples, n_time, st);
     return launch_mfma(d, samples, n_time, st);
 }
@@ -692,6 +693,7 @@ void apply_config(SubDev& d, const SubDev& c) {
     d.bg_tb = c.bg_tb;
     d.KS = c.KS;
     d.KK = c.KK;
+    d.dir_chunks = c.dir_chunks;
 }
 
 std::string cand_name(const SubDev& c) {
@@ -714,7 +716,8 @@ epic_status tune_forms(epic_plan_s* p, hipStream_t st) {
         const SubDev& d = h.dev;
         const int64_t Tn = std::min<int64_t>(p->desc.max_time, 64);
         int64_t S = 1;
-        for (const SubDev& c : h.cands) S = std::max<int64_t>(S, choose_slots(c, Tn));
+        for (const SubDev& c : h.cands)
+            S = std::max<int64_t>(S, c.gridder == EPIC_GRID_DIRECT_GEMM ? c.dir_chunks : choose_slots(c, Tn));
         uint8_t* in = nullptr;
         float* slots = nullptr;
         const size_t in_bytes = (size_t)Tn * d.C * d.A * d.P;
@@ -940,7 +943,7 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if (bs == EPIC_E_UNSUPPORTED) h.tune = false;
             else if (bs != EPIC_OK) return bs;
         }
-        if (d.gridder != EPIC_GRID_GATHER) {
+        if (d.gridder == EPIC_GRID_DENSE_GEMM || d.gridder == EPIC_GRID_BLOCK_GEMM) {
             // real weights shared by both pols (or single pol) only
             if (!(d.wmode == kWShared || (d.P == 1 && d.wmode == kWReal))) return EPIC_E_UNSUPPORTED;
             epic_status bs = build_bgemm(h, d.gridder == EPIC_GRID_DENSE_GEMM);
@@ -980,9 +983,10 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         SubHost& h = p->subs[k];
         SubDev& d = h.dev;
         const int dev_or_none = p->dry_run ? -1 : p->device;
-        hipError_t e = (d.precision == EPIC_FP32)          ? fp32_configure(d, dev_or_none, p->num_cu)
-                       : (d.gridder != EPIC_GRID_GATHER) ? bg_configure(d, dev_or_none, p->num_cu)
-                                                         : mfma_configure(d, dev_or_none, p->num_cu);
+        hipError_t e = (d.precision == EPIC_FP32)                ? fp32_configure(d, dev_or_none, p->num_cu)
+                       : (d.gridder == EPIC_GRID_DIRECT_GEMM) ? direct_configure(d, p->num_cu, desc->max_time)
+                       : (d.gridder != EPIC_GRID_GATHER)      ? bg_configure(d, dev_or_none, p->num_cu)
+                                                              : mfma_configure(d, dev_or_none, p->num_cu);
         if (e == hipErrorNotSupported) return EPIC_E_UNSUPPORTED;
         if (e != hipSuccess) return hip_status(e);
         // autotuner candidates: the other placement of the gather program, and
@@ -996,11 +1000,16 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
                 b.gridder = EPIC_GRID_BLOCK_GEMM;
                 if (bg_configure(b, dev_or_none, p->num_cu, tb) == hipSuccess) h.cands.push_back(b);
             }
+            SubDev dir = d;
+            dir.gridder = EPIC_GRID_DIRECT_GEMM;
+            if (direct_configure(dir, p->num_cu, desc->max_time) == hipSuccess) h.cands.push_back(dir);
         }
-        // slots for whichever form runs (unused ones stay zero)
-        d.S = choose_slots(d, desc->max_time);
+        // slots for whichever form runs (unused ones stay zero); the direct
+        // form's are its time chunks
+        d.S = d.gridder == EPIC_GRID_DIRECT_GEMM ? d.dir_chunks : choose_slots(d, desc->max_time);
         if (p->can_batch) d.S = std::max(d.S, choose_slots(p->bdev[k], desc->max_time));
-        for (const SubDev& c : h.cands) d.S = std::max(d.S, choose_slots(c, desc->max_time));
+        for (const SubDev& c : h.cands)
+            d.S = std::max(d.S, c.gridder == EPIC_GRID_DIRECT_GEMM ? c.dir_chunks : choose_slots(c, desc->max_time));
         p->weights.push_back(p->can_batch ? model_weight(h) : 1);
         // size checks (also in dry run)
         const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
@@ -1039,14 +1048,22 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         if ((s = dalloc(p, &d.slots, nslot)) != EPIC_OK) return s;
         if ((s = hip_status(hipMemsetAsync(d.slots, 0, nslot * sizeof(float), st))) != EPIC_OK) return s;
         if ((s = hip_status(launch_twiddles(d, st))) != EPIC_OK) return s;
-        if (d.precision != EPIC_FP32) {
+        if (d.precision != EPIC_FP32 && d.KK > 0) {   // the transform matrix of the grid-and-FFT forms
             uint16_t* m = nullptr;
             if ((s = dalloc(p, &m, (size_t)2 * d.N * 32 * d.KK)) != EPIC_OK) return s;
             d.dft16 = m;
             if ((s = hip_status(launch_dft_matrix(d, st))) != EPIC_OK) return s;
         }
         if ((s = hip_status(launch_entry_weights(d, st))) != EPIC_OK) return s;
-        if (d.gridder != EPIC_GRID_GATHER || h.tune) {
+        bool need_dir = d.gridder == EPIC_GRID_DIRECT_GEMM;
+        for (const SubDev& c : h.cands) need_dir = need_dir || c.gridder == EPIC_GRID_DIRECT_GEMM;
+        if (need_dir) {
+            uint16_t* m = nullptr;
+            if ((s = dalloc(p, &m, (size_t)direct_matrix_halfs(d))) != EPIC_OK) return s;
+            d.dir_m = m;
+            if ((s = hip_status(launch_direct_matrix(d, st))) != EPIC_OK) return s;
+        }
+        if (d.gridder == EPIC_GRID_DENSE_GEMM || d.gridder == EPIC_GRID_BLOCK_GEMM || h.tune) {
             if ((s = upload(p, &d.bg_chans, h.bg_chans, st)) != EPIC_OK) return s;
             if ((s = upload(p, &d.bg_tiles, h.bg_tiles, st)) != EPIC_OK) return s;
             if ((s = upload(p, &d.bg_cells, h.bg_cells, st)) != EPIC_OK) return s;
@@ -1148,7 +1165,7 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
     *out = nullptr;
     if (!desc || desc->n_sub < 1 || desc->n_sub > kMaxSub || !desc->sub) return EPIC_E_ARG;
     if (desc->precision < EPIC_FP32 || desc->precision > EPIC_FP8) return EPIC_E_ARG;
-    if (desc->gridder < EPIC_GRID_AUTO || desc->gridder > EPIC_GRID_BLOCK_GEMM) return EPIC_E_ARG;
+    if (desc->gridder < EPIC_GRID_AUTO || desc->gridder > EPIC_GRID_DIRECT_GEMM) return EPIC_E_ARG;
     if (desc->output != EPIC_OUT_POL && desc->output != EPIC_OUT_STOKES) return EPIC_E_ARG;
     if (desc->max_time < 1 || desc->device < 0) return EPIC_E_ARG;
     if (desc->flags & ~kKnownFlags) return EPIC_E_ARG;
@@ -1165,6 +1182,7 @@ epic_status epic_plan(const epic_plan_desc* desc, void* hip_stream, epic_plan_t*
     // only as the gridding product's operand type
     const bool gemm = desc->gridder == EPIC_GRID_DENSE_GEMM || desc->gridder == EPIC_GRID_BLOCK_GEMM;
     if (gemm && desc->precision == EPIC_FP32) return EPIC_E_UNSUPPORTED;
+    if (desc->gridder == EPIC_GRID_DIRECT_GEMM && desc->precision != EPIC_FP16) return EPIC_E_UNSUPPORTED;
     if (desc->precision == EPIC_FP8 && desc->gridder == EPIC_GRID_GATHER) return EPIC_E_UNSUPPORTED;
     epic_plan_s* p = new (std::nothrow) epic_plan_s();
     if (!p) return EPIC_E_NOMEM;
@@ -1248,7 +1266,8 @@ epic_status epic_image_noalloc(epic_plan_t p, const uint8_t* const* d_samples, i
     size_t need = 0;
     for (size_t k = 0; k < p->subs.size(); ++k) {
         SubDev d = p->subs[k].dev;
-        d.S = choose_slots(d, std::max<int64_t>(n_time, 1));
+        d.S = d.gridder == EPIC_GRID_DIRECT_GEMM ? (int)std::min<int64_t>(d.dir_chunks, std::max<int64_t>(n_time, 1))
+                                                : choose_slots(d, std::max<int64_t>(n_time, 1));
         d.vaa = nullptr;
         off[k] = need;
         need += ((size_t)d.S * d.C * d.NPP * d.N * d.N + 63) & ~(size_t)63;   // 256-byte aligned pieces
@@ -1325,7 +1344,8 @@ epic_status epic_set_gains(epic_plan_t p, int32_t sub, const float* h_gains, voi
         d.gains = d.gains_buf;
     }
     e = launch_entry_weights(d, st);
-    if (e == hipSuccess && d.gridder != EPIC_GRID_GATHER) e = launch_bg_weights(d, st);
+    if (e == hipSuccess && d.bg_w) e = launch_bg_weights(d, st);
+    if (e == hipSuccess && d.dir_m) e = launch_direct_matrix(d, st);
     return check_device(p, e);
 }
 
@@ -1357,7 +1377,10 @@ epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
         info->col_split[k] = p->subs[k].dev.KS;
         info->workgroups[k] = p->batched ? p->bdev[k].grid_wg : p->subs[k].dev.grid_wg;
         info->grid_form[k] = p->subs[k].dev.precision == EPIC_FP32 ? EPIC_GRID_GATHER : p->subs[k].dev.gridder;
-        info->grid_step[k] = p->subs[k].dev.gridder != EPIC_GRID_GATHER ? p->subs[k].dev.bg_tb : 1;
+        const SubDev& dk = p->subs[k].dev;
+        info->grid_step[k] = dk.gridder == EPIC_GRID_DIRECT_GEMM ? 16 / dk.P
+                             : dk.gridder != EPIC_GRID_GATHER    ? dk.bg_tb
+                                                                 : 1;
         info->autocorr_pending[k] = (int32_t)p->ac_pending[k];
         info->grid_blocks[k] = (int64_t)p->subs[k].bg_ents.size();
     }
@@ -1370,6 +1393,7 @@ epic_status epic_debug_schedule(epic_plan_t p, int32_t sub, int64_t n_time, int3
     if (!valid_plan(p) || !h_wg || !h_slot || sub < 0 || sub >= (int32_t)p->subs.size()) return EPIC_E_ARG;
     if (n_time < 1 || n_time > p->desc.max_time) return EPIC_E_ARG;
     const SubDev& d = p->batched ? p->bdev[sub] : p->subs[sub].dev;
+    if (d.gridder == EPIC_GRID_DIRECT_GEMM) return EPIC_E_UNSUPPORTED;   // its own (channel, pixel, time) split
     const int KS = d.KS;
     const int64_t n = (int64_t)d.C * KS * n_time;
     std::fill(h_wg, h_wg + n, -1);

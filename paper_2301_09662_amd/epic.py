@@ -28,13 +28,13 @@ _lib = ctypes.CDLL(_LIB_PATH)
 # ---- enums (include/epic.h) ------------------------------------------------
 EPIC_OK, EPIC_E_ARG, EPIC_E_GEOMETRY, EPIC_E_NOMEM, EPIC_E_DEVICE, EPIC_E_UNSUPPORTED, EPIC_E_STATE = range(7)
 EPIC_FP32, EPIC_FP16, EPIC_FP8 = 0, 1, 2
-EPIC_GRID_AUTO, EPIC_GRID_GATHER, EPIC_GRID_DENSE_GEMM, EPIC_GRID_BLOCK_GEMM = 0, 1, 2, 3
+EPIC_GRID_AUTO, EPIC_GRID_GATHER, EPIC_GRID_DENSE_GEMM, EPIC_GRID_BLOCK_GEMM, EPIC_GRID_DIRECT_GEMM = 0, 1, 2, 3, 4
 EPIC_OUT_POL, EPIC_OUT_STOKES = 0, 1
 EPIC_F_GRAPH, EPIC_F_AUTOTUNE, EPIC_F_DRY_RUN, EPIC_F_REMOVE_AUTOCORR, EPIC_F_COMPLEX_WEIGHTS = 1, 2, 4, 8, 16
 EPIC_F_ONE_LAUNCH = 32
 PRECISIONS = {"fp32": EPIC_FP32, "fp16": EPIC_FP16, "fp8": EPIC_FP8}
 GRIDDERS = {"auto": EPIC_GRID_AUTO, "gather": EPIC_GRID_GATHER, "dense": EPIC_GRID_DENSE_GEMM,
-            "block": EPIC_GRID_BLOCK_GEMM}
+            "block": EPIC_GRID_BLOCK_GEMM, "direct": EPIC_GRID_DIRECT_GEMM}
 
 
 class EpicError(RuntimeError):

@@ -90,8 +90,12 @@ def oracle_channels(cfg: int, T: int, chans=None) -> tuple:
 
 
 def check_invariants(gpu: np.ndarray):
-    """Properties every dual-pol image cube has: finite, XX and YY >= 0, and
-    |XY*|^2 <= XX * YY per pixel (Cauchy-Schwarz), up to FP32 rounding."""
+    """Properties every image cube has: finite, XX (and YY) >= 0, and for
+    dual pol |XY*|^2 <= XX * YY per pixel (Cauchy-Schwarz), up to FP32
+    rounding."""
     assert np.isfinite(gpu).all()
+    if gpu.shape[1] == 1:
+        assert (gpu >= 0).all()
+        return
     assert (gpu[:, 0] >= 0).all() and (gpu[:, 1] >= 0).all()
     assert (gpu[:, 2] ** 2 + gpu[:, 3] ** 2 <= gpu[:, 0] * gpu[:, 1] * (1 + 1e-4) + 1e-3).all()
