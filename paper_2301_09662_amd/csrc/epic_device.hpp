@@ -1,5 +1,5 @@
 // Device helpers shared by the HIP translation units of the library: complex
-// arithmetic, the 4+4-bit decoder and a register-resident 16-point DFT.
+// arithmetic, the 4+4-bit decoder and a register-resident 8-point DFT.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,6 +22,10 @@ __device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
     return acc;
 }
 
+// Two and four FP16 values (a decoded sample, a dual-pol antenna).
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
 // One 4+4-bit complex sample (Sec. 2.1): two two's-complement nibbles, the
 // real part in the high nibble for order 0, in the low nibble for order 1.
 // Every value in [-8, 7] is exact in FP32 (and in FP16 / FP8 e4m3).
@@ -29,6 +33,12 @@ __device__ __forceinline__ float2 unpack44(uint32_t byte, int order) {
     const int hi = ((int)(byte << 24)) >> 28;
     const int lo = ((int)(byte << 28)) >> 28;
     return order == 0 ? make_float2((float)hi, (float)lo) : make_float2((float)lo, (float)hi);
+}
+
+// The same sample held in FP16 (exact: |value| <= 8).
+__device__ __forceinline__ h2v unpack44_h(uint32_t byte, int order) {
+    const float2 v = unpack44(byte, order);
+    return h2v{(_Float16)v.x, (_Float16)v.y};
 }
 
 // Radix-4 butterfly with the positive exponent (exp(+2 pi i nk/4) = i^nk):
@@ -39,31 +49,6 @@ __device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
     c = csub(s0, s1);
     b = make_float2(d0.x - d1.y, d0.y + d1.x);   // d0 + i d1
     d = make_float2(d0.x + d1.y, d0.y - d1.x);   // d0 - i d1
-}
-
-// In-place 16-point DFT X[m] = sum_n z[n] exp(+2 pi i n m / 16), as 4 x 4
-// (index n = 4 n1 + n2, m = m1 + 4 m2).  On return X[m] is held in
-// z[fft16_pos(m)].
-__device__ __forceinline__ constexpr int fft16_pos(int m) { return 4 * (m & 3) + (m >> 2); }
-
-__device__ __forceinline__ void fft16(float2 (&z)[16]) {
-    constexpr float c1 = 0.923879532511286756f;   // cos(pi/8)
-    constexpr float s1 = 0.382683432365089772f;   // sin(pi/8)
-    constexpr float h = 0.707106781186547524f;    // cos(pi/4)
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) dft4(z[n2], z[4 + n2], z[8 + n2], z[12 + n2]);
-    // z[4 m1 + n2] *= exp(+2 pi i n2 m1 / 16)
-    z[5] = cmul(z[5], make_float2(c1, s1));                               // n2=1, m1=1: W^1
-    z[9] = make_float2(h * (z[9].x - z[9].y), h * (z[9].x + z[9].y));     // W^2
-    z[13] = cmul(z[13], make_float2(s1, c1));                             // W^3
-    z[6] = make_float2(h * (z[6].x - z[6].y), h * (z[6].x + z[6].y));     // n2=2, m1=1: W^2
-    z[10] = make_float2(-z[10].y, z[10].x);                               // W^4 = i
-    z[14] = make_float2(-h * (z[14].x + z[14].y), h * (z[14].x - z[14].y));  // W^6
-    z[7] = cmul(z[7], make_float2(s1, c1));                               // n2=3, m1=1: W^3
-    z[11] = make_float2(-h * (z[11].x + z[11].y), h * (z[11].x - z[11].y));  // W^6
-    z[15] = cmul(z[15], make_float2(-c1, -s1));                           // W^9
-#pragma unroll
-    for (int m1 = 0; m1 < 4; ++m1) dft4(z[4 * m1], z[4 * m1 + 1], z[4 * m1 + 2], z[4 * m1 + 3]);
 }
 
 // In-place 8-point DFT X[m] = sum_n z[n] exp(+2 pi i n m / 8), as 4 x 2

@@ -15,14 +15,30 @@ namespace epic {
 // Gaussian kernel).
 constexpr int kWComplex = 0, kWReal = 1, kWShared = 2;
 
+// Decoded samples of one antenna, held in FP32 (float2 per pol) or FP16
+// (h2v per pol; the 4-bit values are exact, and the FMAs below convert them
+// on the fly, so both give the same sums while FP16 halves the LDS traffic).
+__device__ __forceinline__ float4 smp_both(const float2* __restrict__ s, int a) {
+    return reinterpret_cast<const float4*>(s)[a];
+}
+__device__ __forceinline__ float4 smp_both(const h2v* __restrict__ s, int a) {
+    const h4v h = reinterpret_cast<const h4v*>(s)[a];
+    return make_float4((float)h[0], (float)h[1], (float)h[2], (float)h[3]);
+}
+__device__ __forceinline__ float2 smp_one(const float2* __restrict__ s, int a) { return s[a]; }
+__device__ __forceinline__ float2 smp_one(const h2v* __restrict__ s, int a) {
+    const h2v h = s[a];
+    return make_float2((float)h[0], (float)h[1]);
+}
+
 // ---- gather gridding of one group of kGroup entries ------------------------
-template <int P, int WM>
+template <int P, int WM, typename SmpT>
 __device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float4* __restrict__ w,
-                                             const uint2 ia, const float2* __restrict__ smp) {
+                                             const uint2 ia, const SmpT* __restrict__ smp) {
     const int a[4] = {(int)(ia.x & 0xFFFFu), (int)(ia.x >> 16), (int)(ia.y & 0xFFFFu), (int)(ia.y >> 16)};
     if constexpr (P == 2) {
-        const float4* s4 = reinterpret_cast<const float4*>(smp);
-        const float4 s0 = s4[a[0]], s1 = s4[a[1]], s2 = s4[a[2]], s3 = s4[a[3]];
+        const float4 s0 = smp_both(smp, a[0]), s1 = smp_both(smp, a[1]), s2 = smp_both(smp, a[2]),
+                     s3 = smp_both(smp, a[3]);
         if constexpr (WM == kWShared) {
             const float4 ww = w[0];   // (w0, w1, w2, w3), both pols
             gx.x = fmaf(ww.x, s0.x, gx.x); gx.y = fmaf(ww.x, s0.y, gx.y);
@@ -53,7 +69,8 @@ __device__ __forceinline__ void gather_group(float2& gx, float2& gy, const float
             }
         }
     } else {
-        const float2 s0 = smp[a[0]], s1 = smp[a[1]], s2 = smp[a[2]], s3 = smp[a[3]];
+        const float2 s0 = smp_one(smp, a[0]), s1 = smp_one(smp, a[1]), s2 = smp_one(smp, a[2]),
+                     s3 = smp_one(smp, a[3]);
         if constexpr (WM != kWComplex) {
             const float4 ww = w[0];
             gx.x = fmaf(ww.x, s0.x, gx.x); gx.y = fmaf(ww.x, s0.y, gx.y);

@@ -28,6 +28,17 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // Row padding (halfs) of the matrix-core operand buffers in LDS.
 constexpr int kPadH = 8;
 
+// Column-owner form: wave w owns image columns 16w..16w+15 for every image
+// row; its row pass produces exactly the transformed rows of those columns,
+// which stay in registers as the column pass's operand, so the row-pass result
+// never goes through LDS and a spectrum needs one barrier instead of two.  It
+// holds the column-pass operand of every image row in registers, which at
+// N = 48 and 64 costs a resident workgroup per CU: measured on the 256-antenna
+// station (N = 64) it ran 0.63 ms against 0.59-0.61 ms for the row-owner
+// form, so it is used for N = 32 only (0.010 against 0.012 ms on the
+// 16-antenna array).
+constexpr bool own_form(int N, int KK) { return N <= 32 && (N / 16) * KK <= 8; }
+
 template <int N_, int KK_>
 struct MShape {
     static constexpr int N = N_;
@@ -45,6 +56,8 @@ struct MShape {
     static constexpr int NT1 = (TILES1 + WAVES - 1) / WAVES;   // row-pass output tiles per wave
     // waves beyond TILES1 / NT1 (grids above 128) sit the row pass out
     static constexpr bool ALL_ROW_WAVES = TILES1 == WAVES * NT1;
+    static constexpr bool OWN = own_form(N, KK);
+    static constexpr int RT = N / 16;              // image row tiles (column-owner form)
     // register budget: three waves per SIMD (168 VGPRs) for the small shapes,
     // where the extra resident workgroup outweighs a few spills (measured:
     // station N = 64, KK = 2: 0.75 -> 0.64 ms); the compiler's choice otherwise
@@ -161,6 +174,126 @@ __device__ __forceinline__ void col_pass(const _Float16* __restrict__ s_B2, cons
             }
         }
     }
+}
+
+// ---- column-owner form -------------------------------------------------------
+// Column-pass operand of the column-owner form: every image row tile rt, real
+// (h = 0) and imaginary (h = 1) output rows.  The depth is permuted to match
+// the registers the row pass leaves: slot e of lane quarter l4 in 32-deep step
+// ks is depth 16 (2 ks + e / 4) + 4 l4 + e % 4.
+template <class Sh>
+__device__ __forceinline__ void load_col_fragments_own(half8 (&a2)[2][Sh::RT][Sh::KK],
+                                                       const _Float16* __restrict__ dft, int l16, int l4) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int rt = 0; rt < Sh::RT; ++rt)
+#pragma unroll
+            for (int ks = 0; ks < Sh::KK; ++ks) {
+                const _Float16* row = dft + (size_t)(h * Sh::N + 16 * rt + l16) * Sh::K2 + 32 * ks + 4 * l4;
+                const half4 lo = *reinterpret_cast<const half4*>(row);
+                const half4 hi = *reinterpret_cast<const half4*>(row + 16);
+                a2[h][rt][ks] = half8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            }
+}
+
+// Row-pass operand of wave w in the column-owner form: the DFT rows of its
+// real (u = 0) and imaginary (u = 1) output columns 16w + l16.
+template <class Sh>
+__device__ __forceinline__ void load_row_fragments_own(half8 (&b1)[2][Sh::KK], const _Float16* __restrict__ dft,
+                                                       int w, int l16, int l4) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ks = 0; ks < Sh::KK; ++ks)
+            b1[u][ks] = *reinterpret_cast<const half8*>(dft + (size_t)(u * Sh::N + 16 * w + l16) * Sh::K2 + 32 * ks +
+                                                        8 * l4);
+}
+
+// Row pass and column pass of one spectrum in the column-owner form.  s_A1
+// holds the gridded window with pol p's rows at p * KPAD + r (rows r >= R are
+// zero).  For each pol the row pass yields the 2 KK 16-row tiles of the
+// wave's transformed columns -- tile j: real part (j < KK) or imaginary part
+// of rows 16 (j mod KK) .. -- which, rounded to FP16 and paired (2 ks, 2 ks + 1),
+// are the column pass's depth steps ks; then the products of Eq. 5 are added
+// into acc[rt][e][k] for image row 16 rt + 4 l4 + e, image column 16 w + l16.
+template <class Sh, int P>
+__device__ __forceinline__ void own_pass(const _Float16* __restrict__ s_A1, const half8 (&b1)[2][Sh::KK],
+                                         const half8 (&a2)[2][Sh::RT][Sh::KK],
+                                         float (&acc)[Sh::RT][4][(P == 2) ? 4 : 1], int R, int l16, int l4) {
+    constexpr int KK = Sh::KK, KPAD = Sh::KPAD, A1P = Sh::A1P;
+    half8 yb[P][KK];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        floatx4 dt[2 * KK];
+#pragma unroll
+        for (int mt = 0; mt < KK; ++mt) {
+            dt[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            dt[KK + mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (16 * mt < R) {   // uniform: tiles past the window rows are zero
+                half8 af[KK];
+#pragma unroll
+                for (int ks = 0; ks < KK; ++ks)
+                    af[ks] = *reinterpret_cast<const half8*>(s_A1 + (p * KPAD + 16 * mt + l16) * A1P + 32 * ks + 8 * l4);
+#pragma unroll
+                for (int ks = 0; ks < KK; ++ks) {
+                    dt[mt] = mfma16(af[ks], b1[0][ks], dt[mt]);
+                    dt[KK + mt] = mfma16(af[ks], b1[1][ks], dt[KK + mt]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < KK; ++ks) {
+            const floatx4 a = dt[2 * ks], b = dt[2 * ks + 1];
+            yb[p][ks] = half8{(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3],
+                              (_Float16)b[0], (_Float16)b[1], (_Float16)b[2], (_Float16)b[3]};
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < Sh::RT; ++rt) {
+        floatx4 er[P], ei[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            er[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ei[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KK; ++ks) {
+                er[p] = mfma16(a2[0][rt][ks], yb[p][ks], er[p]);
+                ei[p] = mfma16(a2[1][rt][ks], yb[p][ks], ei[p]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float xr = er[0][e], xi = ei[0][e];
+            acc[rt][e][0] = fmaf(xr, xr, fmaf(xi, xi, acc[rt][e][0]));
+            if constexpr (P == 2) {
+                const float yr = er[1][e], yi = ei[1][e];
+                acc[rt][e][1] = fmaf(yr, yr, fmaf(yi, yi, acc[rt][e][1]));
+                acc[rt][e][2] = fmaf(xr, yr, fmaf(xi, yi, acc[rt][e][2]));
+                acc[rt][e][3] = fmaf(xi, yr, fmaf(-xr, yi, acc[rt][e][3]));
+            }
+        }
+    }
+}
+
+// Segment flush of the column-owner form (wave w: image columns 16w..).
+template <class Sh, int P>
+__device__ __forceinline__ void flush_slot_own(float* __restrict__ slots, int slot, int C, int c,
+                                               const float (&acc)[Sh::RT][4][(P == 2) ? 4 : 1], int w, int l16,
+                                               int l4) {
+    constexpr int N = Sh::N, NPP = (P == 2) ? 4 : 1;
+    float* base_p = slots + ((int64_t)slot * C + c) * NPP * N * N;
+    int ii = 16 * w + l16 + N / 2;
+    if (ii >= N) ii -= N;
+#pragma unroll
+    for (int rt = 0; rt < Sh::RT; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int j = 16 * rt + 4 * l4 + e + N / 2;
+            if (j >= N) j -= N;
+#pragma unroll
+            for (int k = 0; k < NPP; ++k) base_p[((int64_t)k * N + j) * N + ii] += acc[rt][e][k];
+        }
 }
 
 // Add a segment's sums into its slot of channel c; frequency bin -> pixel

@@ -31,14 +31,14 @@ struct SegCtx {
     float* slots;             // [S][C][NPP][N][N]
     int C, A;
     int WP;                   // pitch encoded in the gather program's cell offsets
-    int M1max;                // rows of the row-pass operand (multiple of 16)
+    int M1max;                // rows of the row-pass operand (multiple of 16), per buffer
     int nibble_order, prog_lds;
 };
 
 // LDS carve-up shared by every segment a workgroup runs.
 struct LdsMap {
     uint32_t off_w, off_gant, off_desc, off_smp, off_A1, off_B2;
-    int smp_stride;           // float2 elements between the two sample buffers
+    int smp_stride;           // samples (h2v) between the two sample buffers
 };
 
 struct MfmaArgs {
@@ -50,11 +50,11 @@ struct MfmaArgs {
 };
 
 // Gather gridding of every non-empty window cell (FP32 sums), stored as the
-// FP16 row-pass operand: row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)].
+// FP16 row-pass operand: row p*prow + r, columns [Re G(r, 0..) | Im G(r, 0..)].
 // The program pointers are all in LDS or all in global memory.
 template <int P, int WM, int KPAD, int A1P, int TH, typename DescP, typename AntP, typename WP_>
 __device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int n_cell,
-                                             const float2* __restrict__ smp, int WP, int R4, _Float16* s_A1) {
+                                             const h2v* __restrict__ smp, int WP, int prow, _Float16* s_A1) {
     constexpr int GF4 = group_f4<P, WM>();
     for (int k = threadIdx.x; k < n_cell; k += TH) {
         const uint2 d = desc[k];
@@ -70,8 +70,8 @@ __device__ __forceinline__ void gather_cells(DescP desc, AntP gant, WP_ wts, int
         dst[0] = (_Float16)gx.x;
         dst[KPAD] = (_Float16)gx.y;
         if constexpr (P == 2) {
-            dst[R4 * A1P] = (_Float16)gy.x;
-            dst[R4 * A1P + KPAD] = (_Float16)gy.y;
+            dst[prow * A1P] = (_Float16)gy.x;
+            dst[prow * A1P + KPAD] = (_Float16)gy.y;
         }
     }
 }
@@ -89,6 +89,7 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
     using Sh = MShape<N_, KK_>;
     constexpr int N = Sh::N, KK = Sh::KK, KPAD = Sh::KPAD, K2 = Sh::K2, KS = Sh::KS, NK = Sh::NK;
     constexpr int IT = Sh::IT, NT1 = Sh::NT1, A1P = Sh::A1P, B2P = Sh::B2P, WAVES = Sh::WAVES;
+    constexpr bool OWN = Sh::OWN;   // column-owner form (two A1 buffers, no B2)
     constexpr int NPP = (P == 2) ? 4 : 1;
     constexpr int GF4 = group_f4<P, WM>();
     const int tid = threadIdx.x;
@@ -102,14 +103,18 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
     float4* s_w = reinterpret_cast<float4*>(smem + lm.off_w);
     uint2* s_gant = reinterpret_cast<uint2*>(smem + lm.off_gant);
     uint2* s_desc = reinterpret_cast<uint2*>(smem + lm.off_desc);
-    float2* s_smp0 = reinterpret_cast<float2*>(smem + lm.off_smp);   // two sample buffers
-    float2* s_smp1 = s_smp0 + lm.smp_stride;
+    h2v* s_smp0 = reinterpret_cast<h2v*>(smem + lm.off_smp);   // two sample buffers (FP16, exact)
+    h2v* s_smp1 = s_smp0 + lm.smp_stride;
     _Float16* s_A1 = reinterpret_cast<_Float16*>(smem + lm.off_A1);
     _Float16* s_B2 = reinterpret_cast<_Float16*>(smem + lm.off_B2);
 
-    // column-pass operand: rows 16w.. (real part) and N + 16w.. (imaginary part)
+    // column-pass operand: rows 16w.. (real part) and N + 16w.. (imaginary
+    // part); in the column-owner form every row tile
     half8 a2[2][KK];
-    load_col_fragments<Sh>(a2, sc.dft, mw, l16, l4);
+    half8 a2o[2][OWN ? Sh::RT : 1][KK];
+    if constexpr (OWN) load_col_fragments_own<Sh>(a2o, sc.dft, l16, l4);
+    else load_col_fragments<Sh>(a2, sc.dft, mw, l16, l4);
+    const int a1_stride = OWN ? sc.M1max * A1P : 0;   // halfs between the two A1 buffers
 
     const int AP = sc.A * P;
     const bool words = ((AP & 3) == 0) && ((reinterpret_cast<uintptr_t>(sc.samples) & 3) == 0);
@@ -127,30 +132,30 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
     };
     // decode one (t, c) row of A*P bytes into dst: the prefetched words first,
     // any further words straight from memory
-    auto decode = [&](float2* dst, int cc, int64_t tt) {
+    auto decode = [&](h2v* dst, int cc, int64_t tt) {
         if (words) {
 #pragma unroll
             for (int k = 0; k < kPre; ++k) {
                 const int w = tid + k * TH;
                 if (w < nwords) {
                     const uint32_t x = pre[k];
-                    dst[4 * w + 0] = unpack44(x & 0xFFu, sc.nibble_order);
-                    dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, sc.nibble_order);
-                    dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, sc.nibble_order);
-                    dst[4 * w + 3] = unpack44(x >> 24, sc.nibble_order);
+                    dst[4 * w + 0] = unpack44_h(x & 0xFFu, sc.nibble_order);
+                    dst[4 * w + 1] = unpack44_h((x >> 8) & 0xFFu, sc.nibble_order);
+                    dst[4 * w + 2] = unpack44_h((x >> 16) & 0xFFu, sc.nibble_order);
+                    dst[4 * w + 3] = unpack44_h(x >> 24, sc.nibble_order);
                 }
             }
             const uint32_t* row4 = reinterpret_cast<const uint32_t*>(sc.samples + ((int64_t)tt * sc.C + cc) * AP);
             for (int w = tid + kPre * TH; w < nwords; w += TH) {
                 const uint32_t x = row4[w];
-                dst[4 * w + 0] = unpack44(x & 0xFFu, sc.nibble_order);
-                dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, sc.nibble_order);
-                dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, sc.nibble_order);
-                dst[4 * w + 3] = unpack44(x >> 24, sc.nibble_order);
+                dst[4 * w + 0] = unpack44_h(x & 0xFFu, sc.nibble_order);
+                dst[4 * w + 1] = unpack44_h((x >> 8) & 0xFFu, sc.nibble_order);
+                dst[4 * w + 2] = unpack44_h((x >> 16) & 0xFFu, sc.nibble_order);
+                dst[4 * w + 3] = unpack44_h(x >> 24, sc.nibble_order);
             }
         } else {
             const uint8_t* row = sc.samples + ((int64_t)tt * sc.C + cc) * AP;
-            for (int k = tid; k < AP; k += TH) dst[k] = unpack44(row[k], sc.nibble_order);
+            for (int k = tid; k < AP; k += TH) dst[k] = unpack44_h(row[k], sc.nibble_order);
         }
     };
 
@@ -172,7 +177,8 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
         const uint2* g_gant = sc.grp_ant + ci.grp_off;
         const float4* g_w = sc.grp_w + (int64_t)ci.grp_off * GF4;
         half8 b1[NT1][KK];   // row-pass operand for this wave's output tiles
-        load_row_fragments<Sh>(b1, sc.dft, kpart, mw, l16, l4);
+        if constexpr (OWN) load_row_fragments_own<Sh>(b1, sc.dft, mw, l16, l4);
+        else load_row_fragments<Sh>(b1, sc.dft, kpart, mw, l16, l4);
         __syncthreads();   // the previous segment is done with every LDS buffer
         if (prog) {
             for (int k = tid; k < ci.n_grp * GF4; k += TH) s_w[k] = g_w[k];
@@ -183,9 +189,11 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
         // and the padding up to whole MFMA steps are never written again
         {
             uint4* z1 = reinterpret_cast<uint4*>(s_A1);
-            for (int k = tid; k < sc.M1max * A1P / 8; k += TH) z1[k] = make_uint4(0, 0, 0, 0);
-            uint4* z2 = reinterpret_cast<uint4*>(s_B2);
-            for (int k = tid; k < P * NK * B2P / 8; k += TH) z2[k] = make_uint4(0, 0, 0, 0);
+            for (int k = tid; k < (OWN ? 2 : 1) * sc.M1max * A1P / 8; k += TH) z1[k] = make_uint4(0, 0, 0, 0);
+            if constexpr (!OWN) {
+                uint4* z2 = reinterpret_cast<uint4*>(s_B2);
+                for (int k = tid; k < P * NK * B2P / 8; k += TH) z2[k] = make_uint4(0, 0, 0, 0);
+            }
         }
         float acc[IT][4][NPP];
 #pragma unroll
@@ -206,18 +214,22 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
 
         for (int64_t i = 0; i < n; ++i) {
             const int64_t tt = t + i;
-            float2* s_smp = (i & 1) ? s_smp1 : s_smp0;
-            float2* s_nxt = (i & 1) ? s_smp0 : s_smp1;
+            h2v* s_smp = (i & 1) ? s_smp1 : s_smp0;
+            h2v* s_nxt = (i & 1) ? s_smp0 : s_smp1;
 
             // Wave priorities as in the FP32 kernel: the latency-bound gathering
             // and row pass ahead of the column pass of a CU's other workgroups.
             __builtin_amdgcn_s_setprio(2);
             // 2. gather gridding (FP32), stored as the FP16 row-pass operand:
-            //    row p*R4 + r, columns [Re G(r, 0..) | Im G(r, 0..)]
+            //    row p*prow + r, columns [Re G(r, 0..) | Im G(r, 0..)]; the
+            //    column-owner form alternates two buffers and puts each pol
+            //    at a whole number of tiles
+            _Float16* a1 = s_A1 + (i & 1) * a1_stride;
+            const int prow = OWN ? KPAD : R4;
             if (prog)
-                gather_cells<P, WM, KPAD, A1P, TH>(s_desc, s_gant, s_w, n_cell, s_smp, sc.WP, R4, s_A1);
+                gather_cells<P, WM, KPAD, A1P, TH>(s_desc, s_gant, s_w, n_cell, s_smp, sc.WP, prow, a1);
             else
-                gather_cells<P, WM, KPAD, A1P, TH>(g_desc, g_gant, g_w, n_cell, s_smp, sc.WP, R4, s_A1);
+                gather_cells<P, WM, KPAD, A1P, TH>(g_desc, g_gant, g_w, n_cell, s_smp, sc.WP, prow, a1);
             // 1'. decode the next spectrum of this segment into the other buffer
             if (i + 1 < n) {
                 decode(s_nxt, c, tt + 1);
@@ -228,18 +240,31 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
             }
             __syncthreads();
 
-            __builtin_amdgcn_s_setprio(1);
-            // 3a. row pass on the matrix cores -> column-pass operand B2
-            if (mwave) row_pass<Sh, P>(s_A1, s_B2, b1, M1, R4, mw, l16, l4);
-            __syncthreads();
+            if constexpr (OWN) {
+                // 3 + 4. both passes in registers; the next spectrum's gather
+                // writes the other A1 buffer, so one barrier per spectrum
+                // orders everything (this buffer is rewritten only after the
+                // next spectrum's barrier, which every wave reaches after this)
+                __builtin_amdgcn_s_setprio(0);
+                if (mwave) own_pass<Sh, P>(a1, b1, a2o, acc, ci.R, l16, l4);
+            } else {
+                __builtin_amdgcn_s_setprio(1);
+                // 3a. row pass on the matrix cores -> column-pass operand B2
+                if (mwave) row_pass<Sh, P>(s_A1, s_B2, b1, M1, R4, mw, l16, l4);
+                __syncthreads();
 
-            __builtin_amdgcn_s_setprio(0);
-            // 3b + 4. column pass, both pols, products of Eq. 5 into registers
-            if (mwave) col_pass<Sh, P>(s_B2, a2, acc, l16, l4);
+                __builtin_amdgcn_s_setprio(0);
+                // 3b + 4. column pass, both pols, products of Eq. 5 into registers
+                if (mwave) col_pass<Sh, P>(s_B2, a2, acc, l16, l4);
+            }
         }
 
         // add the segment's sums into its slot; bin -> pixel (+N/2 mod N)
-        if (mwave) flush_slot<Sh, P>(sc.slots, slot, sc.C, c, kpart, acc, mw, l16, l4);
+        if constexpr (OWN) {
+            if (mwave) flush_slot_own<Sh, P>(sc.slots, slot, sc.C, c, acc, mw, l16, l4);
+        } else {
+            if (mwave) flush_slot<Sh, P>(sc.slots, slot, sc.C, c, kpart, acc, mw, l16, l4);
+        }
         f += n;
         ++s_ch;
         v += vstep;
@@ -344,22 +369,34 @@ size_t take_aligned(size_t& b, size_t n) {
     return o;
 }
 
-int m1max_of(const SubDev& d) { return (d.P * ((d.Rmax + 3) & ~3) + 15) / 16 * 16; }
+// rows of one row-pass operand buffer: pols at R4 (padded to whole tiles), or
+// at whole tiles KPAD in the column-owner form
+int m1max_of(const SubDev& d) {
+    if (own_form(d.N, d.KK)) return d.P * 16 * d.KK;
+    return (d.P * ((d.Rmax + 3) & ~3) + 15) / 16 * 16;
+}
+
+// LDS bytes of the row-pass operand (two buffers in the column-owner form)
+// and of the column-pass operand (none there)
+size_t a1_bytes(const SubDev& d) {
+    return (size_t)(own_form(d.N, d.KK) ? 2 : 1) * m1max_of(d) * (32 * d.KK + kPadH) * 2;
+}
+size_t b2_bytes(const SubDev& d) {
+    return own_form(d.N, d.KK) ? 0 : (size_t)d.P * (d.N / ks_of(d.N)) * (32 * d.KK + kPadH) * 2;
+}
 
 Layout layout(const SubDev& d, bool prog_lds) {
     Layout L{};
     size_t b = 0;
     const int gf4 = group_f4_of(d.P, d.wmode);
-    const int K2 = 32 * d.KK;
-    const int NK = d.N / ks_of(d.N);
     L.M1max = m1max_of(d);
     L.lm.off_w = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.Gmax * gf4 * 16) : 0;
     L.lm.off_gant = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.Gmax * 8) : 0;
     L.lm.off_desc = prog_lds ? (uint32_t)take_aligned(b, (size_t)d.CellMax * 8) : 0;
-    L.lm.off_smp = (uint32_t)take_aligned(b, (size_t)2 * d.A * d.P * sizeof(float2));
+    L.lm.off_smp = (uint32_t)take_aligned(b, (size_t)2 * d.A * d.P * 4);
     L.lm.smp_stride = d.A * d.P;
-    L.lm.off_A1 = (uint32_t)take_aligned(b, (size_t)L.M1max * (K2 + kPadH) * 2);
-    L.lm.off_B2 = (uint32_t)take_aligned(b, (size_t)d.P * NK * (K2 + kPadH) * 2);
+    L.lm.off_A1 = (uint32_t)take_aligned(b, a1_bytes(d));
+    L.lm.off_B2 = (uint32_t)take_aligned(b, b2_bytes(d));
     L.total = (b + 15) & ~(size_t)15;
     return L;
 }
@@ -518,16 +555,15 @@ hipError_t batch_configure(SubDev* subs, int n_sub, BatchDev& bd, int device, in
         ga = std::max(ga, (size_t)d.Gmax * 8);
         gd = std::max(gd, (size_t)d.CellMax * 8);
         smp = std::max(smp, (size_t)d.A * d.P);
-        const int K2 = 32 * d.KK;
-        a1 = std::max(a1, (size_t)m1max_of(d) * (K2 + kPadH) * 2);
-        b2 = std::max(b2, (size_t)d.P * (d.N / d.KS) * (K2 + kPadH) * 2);
+        a1 = std::max(a1, a1_bytes(d));
+        b2 = std::max(b2, b2_bytes(d));
     }
     auto lay = [&](bool prog, LdsMap& lm) {
         size_t b = 0;
         lm.off_w = prog ? (uint32_t)take_aligned(b, gw) : 0;
         lm.off_gant = prog ? (uint32_t)take_aligned(b, ga) : 0;
         lm.off_desc = prog ? (uint32_t)take_aligned(b, gd) : 0;
-        lm.off_smp = (uint32_t)take_aligned(b, 2 * smp * sizeof(float2));
+        lm.off_smp = (uint32_t)take_aligned(b, 2 * smp * 4);
         lm.smp_stride = (int)smp;
         lm.off_A1 = (uint32_t)take_aligned(b, a1);
         lm.off_B2 = (uint32_t)take_aligned(b, b2);

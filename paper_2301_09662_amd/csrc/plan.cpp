@@ -418,6 +418,14 @@ int choose_slots(const SubDev& d, int64_t max_time) {
     return (int)S;
 }
 
+// Slots a launch of d's form over up to max_time spectra adds into: the
+// direct form's are its time chunks.
+int slots_for(const SubDev& d, int64_t max_time) {
+    if (d.precision != EPIC_FP32 && d.gridder == EPIC_GRID_DIRECT_GEMM)
+        return (int)std::max<int64_t>(1, std::min<int64_t>(d.dir_chunks, max_time));
+    return choose_slots(d, max_time);
+}
+
 // Cost of one spectrum of one virtual channel in the batched launch, from a
 // simple model (CU cycles): MFMA instructions of both transform passes at 4
 // cycles per CU, and VALU lane operations (products, gathering, decoding) at
@@ -433,15 +441,21 @@ int model_weight(const SubHost& h) {
 }
 
 // The batched form of a sub-array: its tables and buffers, with the batched
-// kernel's launch shape.
+// kernel's launch shape (gather gridding, whatever form its dedicated launch
+// was tuned to).
 SubDev batch_view(const SubDev& d, const SubDev& shape) {
     SubDev b = d;
+    b.gridder = EPIC_GRID_GATHER;
+    b.KK = shape.KK;
+    b.KS = shape.KS;
     b.threads = shape.threads;
     b.lds_bytes = shape.lds_bytes;
     b.prog_lds = shape.prog_lds;
     b.grid_wg = shape.grid_wg;
     return b;
 }
+
+hipError_t launch_one(const SubDev& d, const uint8_t* samples, int64_t n_time, hipStream_t st);
 
 // Time of one accumulate call of Tn spectra in either form, on probe inputs
 // and scratch slots (milliseconds, best of three after a warm-up call).
@@ -467,10 +481,10 @@ epic_status time_forms(epic_plan_s* p, hipStream_t st, int64_t Tn, const std::ve
                 if (form == 0) {
                     e = launch_batch(bd, in.data(), n_sub, Tn, st);
                 } else {
-                    for (int s = 0; s < n_sub && e == hipSuccess; ++s) {
+                    for (int s = 0; s < n_sub && e == hipSuccess; ++s) {   // each in its tuned form
                         SubDev d = p->subs[s].dev;
                         d.slots = slots[s];
-                        e = launch_mfma(d, in[s], Tn, st);
+                        e = launch_one(d, in[s], Tn, st);
                     }
                 }
             }
@@ -568,7 +582,7 @@ epic_status autotune_batch(epic_plan_s* p, hipStream_t st, bool choose_form) {
         for (int s = 0; s < n_sub && r2 == EPIC_OK; ++s) {
             const SubDev& d = p->subs[s].dev;
             const size_t ib = (size_t)Tn * d.C * d.A * d.P;
-            int64_t S = std::max(choose_slots(d, Tn), choose_slots(p->bdev[s], Tn));
+            int64_t S = std::max(slots_for(d, Tn), choose_slots(p->bdev[s], Tn));
             const size_t sb = (size_t)S * d.C * d.NPP * d.N * d.N * sizeof(float);
             uint8_t* x = nullptr;
             if (hipMalloc(&x, ib) != hipSuccess || hipMalloc(&slots[s], sb) != hipSuccess) r2 = EPIC_E_NOMEM;
@@ -717,7 +731,7 @@ epic_status tune_forms(epic_plan_s* p, hipStream_t st) {
         const int64_t Tn = std::min<int64_t>(p->desc.max_time, 64);
         int64_t S = 1;
         for (const SubDev& c : h.cands)
-            S = std::max<int64_t>(S, c.gridder == EPIC_GRID_DIRECT_GEMM ? c.dir_chunks : choose_slots(c, Tn));
+            S = std::max<int64_t>(S, slots_for(c, Tn));
         uint8_t* in = nullptr;
         float* slots = nullptr;
         const size_t in_bytes = (size_t)Tn * d.C * d.A * d.P;
@@ -1006,10 +1020,10 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
         }
         // slots for whichever form runs (unused ones stay zero); the direct
         // form's are its time chunks
-        d.S = d.gridder == EPIC_GRID_DIRECT_GEMM ? d.dir_chunks : choose_slots(d, desc->max_time);
+        d.S = slots_for(d, desc->max_time);
         if (p->can_batch) d.S = std::max(d.S, choose_slots(p->bdev[k], desc->max_time));
         for (const SubDev& c : h.cands)
-            d.S = std::max(d.S, c.gridder == EPIC_GRID_DIRECT_GEMM ? c.dir_chunks : choose_slots(c, desc->max_time));
+            d.S = std::max(d.S, slots_for(c, desc->max_time));
         p->weights.push_back(p->can_batch ? model_weight(h) : 1);
         // size checks (also in dry run)
         const double slot_bytes = (double)d.S * d.C * d.NPP * d.N * d.N * 4.0;
@@ -1100,8 +1114,9 @@ epic_status make_plan(const epic_plan_desc* desc, hipStream_t st, epic_plan_s* p
             if (s != EPIC_OK) return s;
         }
     }
-    for (const SubHost& h : p->subs)
-        if (h.dev.gridder != EPIC_GRID_GATHER && p->can_batch) p->can_batch = p->batched = 0;
+    // the batched launch always grids by gathering; a sub-array whose tuned
+    // dedicated form is a GEMM keeps it for the dedicated launches, and the
+    // batch autotuner below times the two launch forms as they would run
     if (p->can_batch) {
         // the batched form shares every table and buffer of the dedicated one
         for (size_t k = 0; k < p->subs.size(); ++k) p->bdev[k] = batch_view(p->subs[k].dev, p->bdev[k]);
@@ -1266,8 +1281,7 @@ epic_status epic_image_noalloc(epic_plan_t p, const uint8_t* const* d_samples, i
     size_t need = 0;
     for (size_t k = 0; k < p->subs.size(); ++k) {
         SubDev d = p->subs[k].dev;
-        d.S = d.gridder == EPIC_GRID_DIRECT_GEMM ? (int)std::min<int64_t>(d.dir_chunks, std::max<int64_t>(n_time, 1))
-                                                : choose_slots(d, std::max<int64_t>(n_time, 1));
+        d.S = slots_for(d, std::max<int64_t>(n_time, 1));
         d.vaa = nullptr;
         off[k] = need;
         need += ((size_t)d.S * d.C * d.NPP * d.N * d.N + 63) & ~(size_t)63;   // 256-byte aligned pieces
@@ -1376,7 +1390,8 @@ epic_status epic_plan_query(epic_plan_t p, epic_plan_info* info) {
         info->weight[k] = p->weights[k];
         info->col_split[k] = p->subs[k].dev.KS;
         info->workgroups[k] = p->batched ? p->bdev[k].grid_wg : p->subs[k].dev.grid_wg;
-        info->grid_form[k] = p->subs[k].dev.precision == EPIC_FP32 ? EPIC_GRID_GATHER : p->subs[k].dev.gridder;
+        info->grid_form[k] = (p->subs[k].dev.precision == EPIC_FP32 || p->batched) ? EPIC_GRID_GATHER
+                                                                                    : p->subs[k].dev.gridder;
         const SubDev& dk = p->subs[k].dev;
         info->grid_step[k] = dk.gridder == EPIC_GRID_DIRECT_GEMM ? 16 / dk.P
                              : dk.gridder != EPIC_GRID_GATHER    ? dk.bg_tb
