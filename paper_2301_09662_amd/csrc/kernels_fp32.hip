@@ -201,8 +201,10 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     float4* s_w = reinterpret_cast<float4*>(smem + a.off_w);
     uint2* s_gant = reinterpret_cast<uint2*>(smem + a.off_gant);
     uint2* s_desc = reinterpret_cast<uint2*>(smem + a.off_desc);
-    float2* s_smp0 = reinterpret_cast<float2*>(smem + a.off_smp);   // one or two sample buffers
-    float2* s_smp1 = a.dbuf ? s_smp0 + a.A * P : s_smp0;
+    // one or two sample buffers, FP16 (exact for 4-bit values; the gather's
+    // FMAs convert on the fly, and the LDS reads are half as wide)
+    h2v* s_smp0 = reinterpret_cast<h2v*>(smem + a.off_smp);
+    h2v* s_smp1 = a.dbuf ? s_smp0 + a.A * P : s_smp0;
     float2* s_G = reinterpret_cast<float2*>(smem + a.off_G);
     float2* s_Y = reinterpret_cast<float2*>(smem + a.off_Y);
     float2* s_tw = reinterpret_cast<float2*>(smem + a.off_tw);
@@ -248,30 +250,30 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 
     // decode one (t, c) row of A*P bytes into dst: the prefetched words first,
     // any further words straight from memory
-    auto decode = [&](float2* dst, int cc, int64_t tt) {
+    auto decode = [&](h2v* dst, int cc, int64_t tt) {
         if (words) {
 #pragma unroll
             for (int k = 0; k < kPrefetch; ++k) {
                 const int w = dtid + k * THREADS;
                 if (w < nwords) {
                     const uint32_t x = pre[k];
-                    dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                    dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                    dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                    dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                    dst[4 * w + 0] = unpack44_h(x & 0xFFu, a.nibble_order);
+                    dst[4 * w + 1] = unpack44_h((x >> 8) & 0xFFu, a.nibble_order);
+                    dst[4 * w + 2] = unpack44_h((x >> 16) & 0xFFu, a.nibble_order);
+                    dst[4 * w + 3] = unpack44_h(x >> 24, a.nibble_order);
                 }
             }
             const uint32_t* row4 = reinterpret_cast<const uint32_t*>(a.samples + ((int64_t)tt * a.C + cc) * AP);
             for (int w = dtid + kPrefetch * THREADS; w < nwords; w += THREADS) {
                 const uint32_t x = row4[w];
-                dst[4 * w + 0] = unpack44(x & 0xFFu, a.nibble_order);
-                dst[4 * w + 1] = unpack44((x >> 8) & 0xFFu, a.nibble_order);
-                dst[4 * w + 2] = unpack44((x >> 16) & 0xFFu, a.nibble_order);
-                dst[4 * w + 3] = unpack44(x >> 24, a.nibble_order);
+                dst[4 * w + 0] = unpack44_h(x & 0xFFu, a.nibble_order);
+                dst[4 * w + 1] = unpack44_h((x >> 8) & 0xFFu, a.nibble_order);
+                dst[4 * w + 2] = unpack44_h((x >> 16) & 0xFFu, a.nibble_order);
+                dst[4 * w + 3] = unpack44_h(x >> 24, a.nibble_order);
             }
         } else {
             const uint8_t* row = a.samples + ((int64_t)tt * a.C + cc) * AP;
-            for (int k = dtid; k < AP; k += THREADS) dst[k] = unpack44(row[k], a.nibble_order);
+            for (int k = dtid; k < AP; k += THREADS) dst[k] = unpack44_h(row[k], a.nibble_order);
         }
     };
 
@@ -324,8 +326,8 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 
         for (int64_t i = 0; i < n; ++i) {
             const int64_t tt = t + i;
-            float2* s_smp = (i & 1) ? s_smp1 : s_smp0;
-            float2* s_nxt = (i & 1) ? s_smp0 : s_smp1;
+            h2v* s_smp = (i & 1) ? s_smp1 : s_smp0;
+            h2v* s_nxt = (i & 1) ? s_smp0 : s_smp1;
 
             // Wave priorities: the gathering and the row pass are chains of
             // dependent LDS reads run by few waves, the column pass is VALU
@@ -493,7 +495,7 @@ Layout layout(const SubDev& d, int KS, bool prog_lds, int bufs) {
     L.off_w = prog_lds ? take((size_t)d.Gmax * gf4 * 16) : 0;
     L.off_gant = prog_lds ? take((size_t)d.Gmax * 8) : 0;
     L.off_desc = prog_lds ? take((size_t)d.CellMax * 8) : 0;
-    L.off_smp = take((size_t)bufs * d.A * d.P * sizeof(float2));
+    L.off_smp = take((size_t)bufs * d.A * d.P * 4);
     L.off_G = take((size_t)d.P * d.Rmax * d.WP * sizeof(float2));
     L.off_Y = take((size_t)d.P * d.Rmax * L.YP * sizeof(float2));
     L.off_tw = take((size_t)d.N * sizeof(float2));
