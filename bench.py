@@ -51,43 +51,54 @@ def algorithmic_flops_per_ct(sub) -> float:
     return grid + fft + prod
 
 
-# Sources of each precision's hot kernel: the counter-based traffic in
-# profiles/traffic.json is reported only while their hash still matches.
+# Sources of each hot-kernel family: the counter-based figures in
+# profiles/traffic.json and profiles/valu.json are reported only while their
+# hash still matches.
 KERNEL_SOURCES = {
     "fp32": ["kernels_fp32.hip", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp", "epic_internal.hpp"],
     "fp16": ["kernels_mfma.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp",
              "epic_internal.hpp"],
     "bgemm": ["kernels_bgemm.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_sched.hpp", "epic_internal.hpp"],
+    "direct": ["kernels_direct.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_gather.hpp", "epic_internal.hpp"],
 }
 
 
-def sources_sha256(precision):
+def kernel_family(precision, info, k=0):
+    """Hot kernel of a plan's sub-array k: the FP32 kernel, the matrix-core
+    gather kernel, the GEMM-gridding kernel (FP16 / FP8) or the direct form."""
+    if precision == "fp32":
+        return "fp32"
+    return {1: "fp16", 2: "bgemm", 3: "bgemm", 4: "direct"}[info["grid_form"][k]]
+
+
+def sources_sha256(family):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES.get(precision, []):
+    for f in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_2301_09662_amd", "csrc", f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 
-def counter_entry(precision, workload, table="traffic.json"):
-    """The committed counter summary of the hot kernel of `precision` on
-    `workload` (profiles/<table>), or None when there is none or the kernel's
-    sources changed since the counters were taken."""
+def counter_entry(family, precision, workload, table="traffic.json"):
+    """The committed counter summary of the `family` kernel running
+    `precision` on `workload` (profiles/<table>, key family:precision:workload),
+    or None when there is none or the kernel's sources changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", table)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        entry = json.load(fh).get("kernels", {}).get(f"{precision}:{workload}")
-    if not entry or entry.get("sources_sha256") != sources_sha256(precision):
+        entry = json.load(fh).get("kernels", {}).get(f"{family}:{precision}:{workload}")
+    if not entry or entry.get("sources_sha256") != sources_sha256(family):
         return None
     return entry
 
 
-def counter_traffic(precision, workload):
+def counter_traffic(family, precision, workload):
     """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs
     (scaled by the plain-copy calibration), or None."""
-    e = counter_entry(precision, workload)
+    e = counter_entry(family, precision, workload)
     return None if e is None else e["bytes_per_launch"]
 
 
@@ -251,7 +262,7 @@ def main():
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-precision legs")
     ap.add_argument("--legs", default="fp16:gather,fp16:block,fp8:block",
                     help="reduced-precision legs of an FP32 workload, precision:gridder, comma-separated")
-    ap.add_argument("--gridder", choices=["auto", "gather", "dense", "block"], default="auto",
+    ap.add_argument("--gridder", choices=["auto", "gather", "dense", "block", "direct"], default="auto",
                     help="gridding form of the workload's own run")
     ap.add_argument("--precision", choices=["fp32", "fp16", "fp8"], default=None,
                     help="override the workload's own precision")
@@ -348,6 +359,7 @@ def main():
         flags = E.EPIC_F_AUTOTUNE | (0 if args.no_graph else E.EPIC_F_GRAPH)
     ms_per_step, kern_ms, img32, info32 = run(precision, args.steps, args.warmup, flags, args.gridder)
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
+    family = kernel_family(precision, info32)
     dtype = {"fp32": "f32", "fp16": "f16 operands, f32 accumulate",
              "fp8": "e4m3 gridding operands, f16 transforms, f32 accumulate"}[precision]
     res = {
@@ -369,12 +381,13 @@ def main():
             "plan": {k: info32[k] for k in ("batched", "can_batch", "form_ms", "autotuned", "graph", "weight",
                                             "slots", "lds_bytes", "grid_form", "grid_step")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": counter_traffic(precision, wl.name),
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": counter_traffic(family, precision, wl.name),
                      "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops_per_launch},
     }
     if res["roofline"]["traffic"] is not None:
         res["roofline"]["hbm_frac"] = res["roofline"]["traffic"] / (kern_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
-    valu = counter_entry(precision, wl.name, "valu.json")
+    res["roofline"]["kernel_family"] = family
+    valu = counter_entry(family, precision, wl.name, "valu.json")
     if valu is not None:
         # floating-point work the kernel executes, from the VALU instruction
         # counters (lanes x flop per instruction), at the measured time
@@ -398,7 +411,11 @@ def main():
                 continue
             p = parity(img_l, lp)
             par[leg] = p
+            fam_l = kernel_family(lp, info_l)
+            tr_l = counter_traffic(fam_l, lp, wl.name)
             legs.append({"form": leg, "precision": lp, "gridder": lg, "grid_step": info_l["grid_step"],
+                         "kernel_family": fam_l, "traffic": tr_l,
+                         "hbm_frac": None if tr_l is None else tr_l / (kern_l * 1e-3) / (HBM_PEAK_GBS * 1e9),
                          "value": samples_per_step / (ms_l * 1e-3), "ms_per_step": ms_l, "kernel_ms": kern_l,
                          "speedup_vs_fp32": ms_per_step / ms_l,
                          "max_rel_image_err_vs_oracle": None if p is None else p["max"],

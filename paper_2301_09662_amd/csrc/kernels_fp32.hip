@@ -53,7 +53,7 @@ struct Fp32Args {
     float* slots;             // [S][C][NPP][N][N]
     float2* efield;           // E-field form: [T][C][P][N][N] output images
     int Rmax, WP;             // window rows (padded), gather-program row pitch
-    uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
+    uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw, off_tq;
     int nibble_order;
     int dbuf;                 // 1: two sample buffers (decode overlaps gridding)
     int grid_wg, wg_per_xcd;
@@ -86,30 +86,29 @@ constexpr int kPrefetch = 1;   // sample words per thread held in registers ahea
 // bounds check; of the last block only its first 1, 2, 4 or 8 inputs (the
 // non-zero part, rounded up) are folded.  Control flow depends only on len
 // (uniform).
-// s_tw is the LDS table exp(+2 pi i r / N); tw holds w_N^{n1 q}, or with
-// TW_LDS the factors are read from s_tw (n1 q < 7 Q < N) and tw is unused.
+// tq is the lane's row of the LDS table of per-q factors: tq[n1] = w_N^{n1 q}
+// (n1 < 8) and tq[8 + n2] = w_Q^{n2 q} (n2 < Q), so every factor is a load at a
+// constant offset from one address.  tw holds w_N^{n1 q} in registers; with
+// TW_LDS the twiddles are read from tq instead and tw is unused.
 //
 // Windows of two or three blocks (the common case) take fold_fixed, which
 // issues every LDS load of the fold before its first product, so a lane
 // waits for LDS once per fold rather than once per block.
 template <int N, bool TW_LDS, int STRIDE, int NB, int LAST>
 __device__ __forceinline__ void fold_fixed(float2 (&z)[8], const float2* __restrict__ v, const float2 (&tw)[8],
-                                           const float2* __restrict__ s_tw, int q) {
+                                           const float2* __restrict__ tq) {
     float2 b[NB - 1][8], w[NB - 1], t[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = v[k * STRIDE];
-    int widx = 0;   // (8 n2 q) mod N
 #pragma unroll
     for (int n2 = 1; n2 < NB; ++n2) {
-        widx += 8 * q;
-        if (widx >= N) widx -= N;
-        w[n2 - 1] = s_tw[widx];
+        w[n2 - 1] = tq[8 + n2];
 #pragma unroll
         for (int k = 0; k < ((n2 == NB - 1) ? LAST : 8); ++k) b[n2 - 1][k] = v[(8 * n2 + k) * STRIDE];
     }
     if constexpr (TW_LDS) {
 #pragma unroll
-        for (int n1 = 1; n1 < 8; ++n1) t[n1] = s_tw[n1 * q];
+        for (int n1 = 1; n1 < 8; ++n1) t[n1] = tq[n1];
     }
 #pragma unroll
     for (int n2 = 1; n2 < NB; ++n2)
@@ -121,41 +120,36 @@ __device__ __forceinline__ void fold_fixed(float2 (&z)[8], const float2* __restr
 
 template <int N, bool TW_LDS, int STRIDE, bool FIXED>
 __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __restrict__ v, int len,
-                                             const float2 (&tw)[8], const float2* __restrict__ s_tw, int q) {
+                                             const float2 (&tw)[8], const float2* __restrict__ tq) {
     const int nb = (len + 7) >> 3;
     const int tail = len - 8 * (nb - 1);   // non-zero inputs of the last block, 1..8
     if (FIXED && nb == 3) {
-        if (tail <= 1) fold_fixed<N, TW_LDS, STRIDE, 3, 1>(z, v, tw, s_tw, q);
-        else if (tail <= 2) fold_fixed<N, TW_LDS, STRIDE, 3, 2>(z, v, tw, s_tw, q);
-        else if (tail <= 4) fold_fixed<N, TW_LDS, STRIDE, 3, 4>(z, v, tw, s_tw, q);
-        else fold_fixed<N, TW_LDS, STRIDE, 3, 8>(z, v, tw, s_tw, q);
+        if (tail <= 1) fold_fixed<N, TW_LDS, STRIDE, 3, 1>(z, v, tw, tq);
+        else if (tail <= 2) fold_fixed<N, TW_LDS, STRIDE, 3, 2>(z, v, tw, tq);
+        else if (tail <= 4) fold_fixed<N, TW_LDS, STRIDE, 3, 4>(z, v, tw, tq);
+        else fold_fixed<N, TW_LDS, STRIDE, 3, 8>(z, v, tw, tq);
         return;
     }
     if (FIXED && nb == 2) {
-        if (tail <= 1) fold_fixed<N, TW_LDS, STRIDE, 2, 1>(z, v, tw, s_tw, q);
-        else if (tail <= 2) fold_fixed<N, TW_LDS, STRIDE, 2, 2>(z, v, tw, s_tw, q);
-        else if (tail <= 4) fold_fixed<N, TW_LDS, STRIDE, 2, 4>(z, v, tw, s_tw, q);
-        else fold_fixed<N, TW_LDS, STRIDE, 2, 8>(z, v, tw, s_tw, q);
+        if (tail <= 1) fold_fixed<N, TW_LDS, STRIDE, 2, 1>(z, v, tw, tq);
+        else if (tail <= 2) fold_fixed<N, TW_LDS, STRIDE, 2, 2>(z, v, tw, tq);
+        else if (tail <= 4) fold_fixed<N, TW_LDS, STRIDE, 2, 4>(z, v, tw, tq);
+        else fold_fixed<N, TW_LDS, STRIDE, 2, 8>(z, v, tw, tq);
         return;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = v[k * STRIDE];
-    int widx = 0;   // (8 n2 q) mod N
     // not unrolled: an unrolled loop lets the compiler hoist every block's LDS
     // loads above the exit test, which costs ~100 registers
 #pragma unroll 1
     for (int n2 = 1; n2 < nb - 1; ++n2) {
-        widx += 8 * q;
-        if (widx >= N) widx -= N;
-        const float2 w = s_tw[widx];
+        const float2 w = tq[8 + n2];
         const float2* vb = v + 8 * n2 * STRIDE;
 #pragma unroll
         for (int k = 0; k < 8; ++k) z[k] = cfma(z[k], vb[k * STRIDE], w);
     }
     if (nb >= 2) {
-        widx += 8 * q;
-        if (widx >= N) widx -= N;
-        const float2 w = s_tw[widx];
+        const float2 w = tq[8 + nb - 1];
         const float2* vb = v + 8 * (nb - 1) * STRIDE;
         z[0] = cfma(z[0], vb[0], w);
         if (tail > 1) z[1] = cfma(z[1], vb[STRIDE], w);
@@ -169,7 +163,7 @@ __device__ __forceinline__ void fold_twiddle(float2 (&z)[8], const float2* __res
         }
     }
 #pragma unroll
-    for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], TW_LDS ? s_tw[n1 * q] : tw[n1]);   // w^0 = 1
+    for (int n1 = 1; n1 < 8; ++n1) z[n1] = cmul(z[n1], TW_LDS ? tq[n1] : tw[n1]);   // w^0 = 1
 }
 
 // EF: write each spectrum's transformed fields (X, Y) to a.efield instead of
@@ -209,6 +203,13 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
     float2* s_Y = reinterpret_cast<float2*>(smem + a.off_Y);
     float2* s_tw = reinterpret_cast<float2*>(smem + a.off_tw);
     for (int k = tid; k < N; k += THREADS) s_tw[k] = a.twiddle[k];
+    // per-q factor rows: [w_N^{n1 q}, n1 < 8 | w_Q^{n2 q} = w_N^{8 n2 q}, n2 < Q]
+    constexpr int TQP = 8 + N / 8;
+    float2* s_tq = reinterpret_cast<float2*>(smem + a.off_tq);
+    for (int k = tid; k < (N / 8) * TQP; k += THREADS) {
+        const int qq = k / TQP, j = k - qq * TQP;
+        s_tq[k] = a.twiddle[(j < 8 ? j * qq : 8 * (j - 8) * qq) % N];
+    }
 
     // per-lane transform constants (q is wave-uniform when a wave holds one q)
     const bool lane_on = tid < LANES;
@@ -379,7 +380,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 const int p = (P == 2 && rr >= R) ? 1 : 0;
                 const int r = rr - p * R;
                 float2 z[8];
-                fold_twiddle<N, true, 1, kSmallGrid>(z, s_G + (p * a.Rmax + r) * a.WP, W, tw, s_tw, qr);
+                fold_twiddle<N, true, 1, kSmallGrid>(z, s_G + (p * a.Rmax + r) * a.WP, W, tw, s_tq + qr * TQP);
                 fft8(z);
                 float2* yrow = s_Y + (p * a.Rmax + r) * YP + qi;
 #pragma unroll
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         float2 X[8];
-                        fold_twiddle<N, kSmallGrid, YP, false>(X, s_Y + p * a.Rmax * YP + kk, R, tw, s_tw, q);
+                        fold_twiddle<N, kSmallGrid, YP, false>(X, s_Y + p * a.Rmax * YP + kk, R, tw, s_tq + q * TQP);
                         fft8(X);
                         float2* out = a.efield + ((tt * a.C + c) * P + p) * (int64_t)N * N;
 #pragma unroll
@@ -427,11 +428,11 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
             // 3b + 4. column pass per pol, products and accumulation in registers
             if (!EF && lane_on) {
                 float2 X[8];
-                fold_twiddle<N, kSmallGrid, YP, false>(X, s_Y + kk, R, tw, s_tw, q);
+                fold_twiddle<N, kSmallGrid, YP, false>(X, s_Y + kk, R, tw, s_tq + q * TQP);
                 fft8(X);
                 if constexpr (P == 2) {
                     float2 Yv[8];
-                    fold_twiddle<N, kSmallGrid, YP, false>(Yv, s_Y + a.Rmax * YP + kk, R, tw, s_tw, q);
+                    fold_twiddle<N, kSmallGrid, YP, false>(Yv, s_Y + a.Rmax * YP + kk, R, tw, s_tq + q * TQP);
                     fft8(Yv);
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
 }
 
 struct Layout {
-    uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw;
+    uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw, off_tq;
     size_t total;
     int YP;
 };
@@ -499,6 +500,7 @@ Layout layout(const SubDev& d, int KS, bool prog_lds, int bufs) {
     L.off_G = take((size_t)d.P * d.Rmax * d.WP * sizeof(float2));
     L.off_Y = take((size_t)d.P * d.Rmax * L.YP * sizeof(float2));
     L.off_tw = take((size_t)d.N * sizeof(float2));
+    L.off_tq = take((size_t)(d.N / 8) * (8 + d.N / 8) * sizeof(float2));
     L.total = (b + 15) & ~(size_t)15;
     return L;
 }
@@ -615,7 +617,7 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.efield = reinterpret_cast<float2*>(efield);
     a.Rmax = d.Rmax; a.WP = d.WP;
     a.off_w = L.off_w; a.off_gant = L.off_gant; a.off_desc = L.off_desc;
-    a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw;
+    a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw; a.off_tq = L.off_tq;
     a.nibble_order = d.nibble_order;
     a.dbuf = d.smp_bufs == 2 ? 1 : 0;
     a.grid_wg = d.grid_wg;
