@@ -113,7 +113,7 @@ __device__ __forceinline__ void row_pass(const _Float16* __restrict__ s_A1, _Flo
                                          const half8 (&b1)[Sh::NT1][Sh::KK], int M1, int R4, int mw, int l16,
                                          int l4) {
     constexpr int KK = Sh::KK, NT1 = Sh::NT1, NK = Sh::NK, A1P = Sh::A1P, B2P = Sh::B2P, KPAD = Sh::KPAD;
-    for (int mt = 0; mt < (M1 + 15) / 16; ++mt) {
+    auto tile = [&](int mt) {
         half8 af[KK];
 #pragma unroll
         for (int ks = 0; ks < KK; ++ks)
@@ -137,6 +137,17 @@ __device__ __forceinline__ void row_pass(const _Float16* __restrict__ s_A1, _Flo
                 *reinterpret_cast<half4*>(s_B2 + (p * NK + iloc) * B2P + part * KPAD + r0) = hv;
             }
         }
+    };
+    if constexpr (KK <= 2) {
+        // at most four tiles: unrolled with a uniform exit, so every tile's
+        // operand loads issue ahead of the products (station FP16 -4 %)
+#pragma unroll
+        for (int mt = 0; mt < (KPAD * P + 15) / 16; ++mt) {
+            if (16 * mt >= M1) break;
+            tile(mt);
+        }
+    } else {
+        for (int mt = 0; mt < (M1 + 15) / 16; ++mt) tile(mt);
     }
 }
 

@@ -291,22 +291,31 @@ __attribute__((amdgpu_waves_per_eu(bg_waves_per_eu<N_, KK_>()))) bg_kernel(BgArg
 
 // Weight scale of the FP8 form: the largest power of two s with s max|w| <= 224
 // (the e4m3 range is 448); scale = {s, 1/s}.  One block.
-__global__ void bg_scale_kernel(const float* __restrict__ grp_w, int64_t n, float* __restrict__ scale) {
+// FP8 weight scale: the largest |w| of the sub-array's entries (a grid-stride
+// maximum per workgroup, combined with an integer maximum on the float bits,
+// which order like the values for |w| >= 0), then scale = 2^e with
+// 224 <= s max|w| < 448 and its inverse.
+__global__ void bg_absmax_kernel(const float* __restrict__ grp_w, int64_t n, unsigned int* __restrict__ bits) {
     __shared__ float red[256];
     float m = 0.f;
-    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) m = fmaxf(m, fabsf(grp_w[k]));
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(grp_w[k]));
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const float mx = red[0] > 0.f ? red[0] : 1.f;
-        const int e = (int)floorf(log2f(224.f / mx));
-        scale[0] = ldexpf(1.f, e);
-        scale[1] = ldexpf(1.f, -e);
-    }
+    if (threadIdx.x == 0) atomicMax(bits, __float_as_uint(red[0]));
+}
+
+__global__ void bg_scale_kernel(float* __restrict__ scale) {
+    if (threadIdx.x != 0) return;
+    const float mx0 = __uint_as_float(reinterpret_cast<unsigned int*>(scale)[0]);
+    const float mx = mx0 > 0.f ? mx0 : 1.f;
+    const int e = (int)floorf(log2f(224.f / mx));
+    scale[0] = ldexpf(1.f, e);
+    scale[1] = ldexpf(1.f, -e);
 }
 
 // Split every gather entry's weight w into the operand parts of its block
@@ -441,8 +450,13 @@ hipError_t bg_configure(SubDev& d, int device, int num_cu, int force_tb) {
 hipError_t launch_bg_weights(const SubDev& d, hipStream_t st) {
     const int64_t n = d.bg_nentries;   // gather entries
     if (d.precision == EPIC_FP8) {
-        bg_scale_kernel<<<dim3(1), dim3(256), 0, st>>>(d.grp_w, n, d.bg_scale);
-        hipError_t e = hipGetLastError();
+        unsigned int* bits = reinterpret_cast<unsigned int*>(d.bg_scale);
+        hipError_t e = launch_zero(d.bg_scale, 1, st);   // the maximum's bits start at +0
+        if (e != hipSuccess) return e;
+        const int64_t nb = std::min<int64_t>(1024, (n + 255) / 256);
+        bg_absmax_kernel<<<dim3((unsigned)std::max<int64_t>(1, nb)), dim3(256), 0, st>>>(d.grp_w, n, bits);
+        bg_scale_kernel<<<dim3(1), dim3(64), 0, st>>>(d.bg_scale);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     const int bs = 256;
