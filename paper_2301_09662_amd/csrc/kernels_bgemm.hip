@@ -289,8 +289,6 @@ __attribute__((amdgpu_waves_per_eu(bg_waves_per_eu<N_, KK_>()))) bg_kernel(BgArg
     }
 }
 
-// Weight scale of the FP8 form: the largest power of two s with s max|w| <= 224
-// (the e4m3 range is 448); scale = {s, 1/s}.  One block.
 // FP8 weight scale: the largest |w| of the sub-array's entries (a grid-stride
 // maximum per workgroup, combined with an integer maximum on the float bits,
 // which order like the values for |w| >= 0), then scale = 2^e with
