@@ -71,4 +71,12 @@ __device__ __forceinline__ void fft8(float2 (&z)[8]) {
     }
 }
 
+// Add a workgroup's sum into its partial-accumulator slot.  On the first
+// call after a reset the slots hold zeros, so the sum is stored without
+// reading the slot first (0 + v == v bitwise: the sums never hold -0).
+__device__ __forceinline__ void slot_put(float* p, float v, bool fresh) {
+    if (fresh) *p = v;
+    else *p += v;
+}
+
 }  // namespace epic

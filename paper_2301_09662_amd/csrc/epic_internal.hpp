@@ -107,6 +107,7 @@ struct SubDev {
     // direct imaging (EPIC_GRID_DIRECT_GEMM): per-channel kernel-image matrix
     void* dir_m = nullptr;            // [C][N^2 / 8][A / 16][2 terms][64 lanes][8] FP16
     int dir_chunks = 1;               // time chunks (partial accumulator slots) of a launch
+    int fresh = 0;                    // per call: the slots hold zeros (stores replace adds)
 };
 
 // One sub-array as seen by the batched (several sub-arrays in one launch)
@@ -129,6 +130,7 @@ struct BatchDev {
     int grid_wg, threads, kkmax, P, wmode, prog_lds, smp_stride;
     size_t lds_bytes;
     uint32_t off[6];
+    int fresh = 0;            // per call: the slots hold zeros (stores replace adds)
 };
 
 // ---- launchers (defined in the .hip translation units) -----------------

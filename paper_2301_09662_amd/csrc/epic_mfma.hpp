@@ -19,6 +19,8 @@
 
 #include <cstdint>
 
+#include "epic_device.hpp"
+
 namespace epic {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -291,7 +293,7 @@ __device__ __forceinline__ void own_pass(const _Float16* __restrict__ s_A1, cons
 template <class Sh, int P>
 __device__ __forceinline__ void flush_slot_own(float* __restrict__ slots, int slot, int C, int c,
                                                const float (&acc)[Sh::RT][4][(P == 2) ? 4 : 1], int w, int l16,
-                                               int l4) {
+                                               int l4, bool fresh) {
     constexpr int N = Sh::N, NPP = (P == 2) ? 4 : 1;
     float* base_p = slots + ((int64_t)slot * C + c) * NPP * N * N;
     int ii = 16 * w + l16 + N / 2;
@@ -303,7 +305,7 @@ __device__ __forceinline__ void flush_slot_own(float* __restrict__ slots, int sl
             int j = 16 * rt + 4 * l4 + e + N / 2;
             if (j >= N) j -= N;
 #pragma unroll
-            for (int k = 0; k < NPP; ++k) base_p[((int64_t)k * N + j) * N + ii] += acc[rt][e][k];
+            for (int k = 0; k < NPP; ++k) slot_put(&base_p[((int64_t)k * N + j) * N + ii], acc[rt][e][k], fresh);
         }
 }
 
@@ -312,7 +314,7 @@ __device__ __forceinline__ void flush_slot_own(float* __restrict__ slots, int sl
 template <class Sh, int P>
 __device__ __forceinline__ void flush_slot(float* __restrict__ slots, int slot, int C, int c, int kpart,
                                            const float (&acc)[Sh::IT][4][(P == 2) ? 4 : 1], int mw, int l16,
-                                           int l4) {
+                                           int l4, bool fresh) {
     constexpr int N = Sh::N, NPP = (P == 2) ? 4 : 1;
     float* base_p = slots + ((int64_t)slot * C + c) * NPP * N * N;
 #pragma unroll
@@ -324,7 +326,7 @@ __device__ __forceinline__ void flush_slot(float* __restrict__ slots, int slot, 
             int j = 16 * mw + 4 * l4 + e + N / 2;
             if (j >= N) j -= N;
 #pragma unroll
-            for (int k = 0; k < NPP; ++k) base_p[((int64_t)k * N + j) * N + ii] += acc[it][e][k];
+            for (int k = 0; k < NPP; ++k) slot_put(&base_p[((int64_t)k * N + j) * N + ii], acc[it][e][k], fresh);
         }
     }
 }

@@ -80,6 +80,7 @@ struct BgArgs {
     const float* scale;       // [2]: weight scale, its inverse
     const _Float16* dft;      // [2N][K2] real-form DFT matrix
     float* slots;             // [S][C][NPP][N][N]
+    int fresh;                // 1: the slots hold zeros, store instead of add
     int64_t T;
     int C, A, nibble_order, TB, nablk, V;
     uint32_t off_E, off_A1, off_B2;
@@ -281,7 +282,7 @@ __attribute__((amdgpu_waves_per_eu(bg_waves_per_eu<N_, KK_>()))) bg_kernel(BgArg
                 if (u + 1 < nb) __syncthreads();
             }
         }
-        flush_slot<Sh, P>(a.slots, slot, a.C, c, kpart, acc, mw, l16, l4);
+        flush_slot<Sh, P>(a.slots, slot, a.C, c, kpart, acc, mw, l16, l4, a.fresh != 0);
         f += n;
         ++s_ch;
         v += KS;
@@ -482,6 +483,7 @@ hipError_t launch_bgemm(const SubDev& d, const uint8_t* samples, int64_t n_time,
     a.scale = d.bg_scale;
     a.dft = reinterpret_cast<const _Float16*>(d.dft16);
     a.slots = d.slots;
+    a.fresh = d.fresh;
     a.T = n_time;
     a.C = d.C; a.A = d.A; a.nibble_order = d.nibble_order; a.TB = d.bg_tb; a.nablk = d.bg_nablk;
     a.V = d.C * d.KS;

@@ -40,6 +40,7 @@ struct DirArgs {
     float* slots;             // [S][C][NPP][N][N]
     int64_t T;
     int C, A, N, nblk, ntile, groups, chunks, nibble_order;
+    int fresh;                // 1: the slots hold zeros, store instead of add
     uint32_t off_E;           // LDS: two buffers of [blk][64 lanes] half8
 };
 
@@ -170,10 +171,10 @@ __global__ void __launch_bounds__(64 * kDirWaves) direct_kernel(DirArgs a) {
             const int q = tile[k] * 8 + 2 * l4 + s;   // pixel j * N + i
             if constexpr (P == 2) {
                 const int pa = l16 == 0 ? 0 : 1, pb = l16 == 0 ? 2 : 3;   // XX*, Re XY* / YY*, Im XY*
-                out[(int64_t)pa * NN + q] += acc[k][2 * s];
-                out[(int64_t)pb * NN + q] += acc[k][2 * s + 1];
+                slot_put(&out[(int64_t)pa * NN + q], acc[k][2 * s], a.fresh != 0);
+                slot_put(&out[(int64_t)pb * NN + q], acc[k][2 * s + 1], a.fresh != 0);
             } else {
-                out[q] += acc[k][s];
+                slot_put(&out[q], acc[k][s], a.fresh != 0);
             }
         }
     }
@@ -298,6 +299,7 @@ hipError_t launch_direct(const SubDev& d, const uint8_t* samples, int64_t n_time
     a.groups = dir_groups(d);
     a.chunks = (int)std::min<int64_t>(d.dir_chunks, n_time);
     a.nibble_order = d.nibble_order;
+    a.fresh = d.fresh;
     a.off_E = 0;
     DirFn fn = dir_select(d.P, a.nblk);
     if (!fn) return hipErrorNotSupported;

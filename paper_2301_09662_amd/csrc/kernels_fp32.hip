@@ -56,6 +56,7 @@ struct Fp32Args {
     uint32_t off_w, off_gant, off_desc, off_smp, off_G, off_Y, off_tw, off_tq;
     int nibble_order;
     int dbuf;                 // 1: two sample buffers (decode overlaps gridding)
+    int fresh;                // 1: the slots hold zeros, store instead of add
     int grid_wg, wg_per_xcd;
 };
 
@@ -467,7 +468,7 @@ __global__ void __launch_bounds__(Shape<N_>::THREADS)
                 int j = q + Q * m + N / 2;
                 if (j >= N) j -= N;
 #pragma unroll
-                for (int k = 0; k < NPP; ++k) base[((int64_t)k * N + j) * N + ii] += acc[m][k];
+                for (int k = 0; k < NPP; ++k) slot_put(&base[((int64_t)k * N + j) * N + ii], acc[m][k], a.fresh != 0);
             }
         }
         f += n;
@@ -620,6 +621,7 @@ hipError_t launch_fp32(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.off_smp = L.off_smp; a.off_G = L.off_G; a.off_Y = L.off_Y; a.off_tw = L.off_tw; a.off_tq = L.off_tq;
     a.nibble_order = d.nibble_order;
     a.dbuf = d.smp_bufs == 2 ? 1 : 0;
+    a.fresh = d.fresh;
     a.grid_wg = d.grid_wg;
     a.wg_per_xcd = (d.grid_wg + 7) / 8;
     KernelFn fn = select_kernel(d.N, d.P, d.wmode, prog, efield != nullptr);

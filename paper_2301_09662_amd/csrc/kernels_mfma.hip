@@ -33,6 +33,7 @@ struct SegCtx {
     int WP;                   // pitch encoded in the gather program's cell offsets
     int M1max;                // rows of the row-pass operand (multiple of 16), per buffer
     int nibble_order, prog_lds;
+    int fresh;                // 1: the slots hold zeros, store instead of add
 };
 
 // LDS carve-up shared by every segment a workgroup runs.
@@ -261,9 +262,9 @@ __device__ __forceinline__ void mfma_run(const SegCtx& sc, const LdsMap& lm, uns
 
         // add the segment's sums into its slot; bin -> pixel (+N/2 mod N)
         if constexpr (OWN) {
-            if (mwave) flush_slot_own<Sh, P>(sc.slots, slot, sc.C, c, acc, mw, l16, l4);
+            if (mwave) flush_slot_own<Sh, P>(sc.slots, slot, sc.C, c, acc, mw, l16, l4, sc.fresh != 0);
         } else {
-            if (mwave) flush_slot<Sh, P>(sc.slots, slot, sc.C, c, kpart, acc, mw, l16, l4);
+            if (mwave) flush_slot<Sh, P>(sc.slots, slot, sc.C, c, kpart, acc, mw, l16, l4, sc.fresh != 0);
         }
         f += n;
         ++s_ch;
@@ -306,6 +307,7 @@ struct BatchArgs {
     int n_sub;
     int64_t T;
     int grid_wg, wg_per_xcd;
+    int fresh;                // 1: the slots hold zeros, store instead of add
 };
 
 // (N, KK) shapes a batched launch can run
@@ -338,6 +340,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchArgs a) {
             sc.grp_w = reinterpret_cast<const float4*>(bs.grp_w);
             sc.dft = reinterpret_cast<const _Float16*>(bs.dft);
             sc.slots = bs.slots;
+            sc.fresh = a.fresh;
             sc.C = bs.C; sc.A = bs.A; sc.WP = bs.WP; sc.M1max = bs.M1max;
             sc.nibble_order = bs.nibble_order; sc.prog_lds = bs.prog_lds;
             switch (bs.N * 8 + bs.KK) {
@@ -523,6 +526,7 @@ hipError_t launch_mfma(const SubDev& d, const uint8_t* samples, int64_t n_time, 
     a.sc.grp_w = reinterpret_cast<const float4*>(d.grp_w);
     a.sc.dft = reinterpret_cast<const _Float16*>(d.dft16);
     a.sc.slots = d.slots;
+    a.sc.fresh = d.fresh;
     a.sc.C = d.C; a.sc.A = d.A; a.sc.WP = d.WP; a.sc.M1max = L.M1max;
     a.sc.nibble_order = d.nibble_order; a.sc.prog_lds = d.prog_lds;
     a.lm = L.lm;
@@ -634,6 +638,7 @@ hipError_t launch_batch(const BatchDev& bd, const uint8_t* const* samples, int n
     a.lm.off_w = bd.off[0]; a.lm.off_gant = bd.off[1]; a.lm.off_desc = bd.off[2];
     a.lm.off_smp = bd.off[3]; a.lm.off_A1 = bd.off[4]; a.lm.off_B2 = bd.off[5];
     a.lm.smp_stride = bd.smp_stride;
+    a.fresh = bd.fresh;
     BatchFn fn = select_batch(bd.P, bd.wmode);
     hipLaunchKernelGGL(fn, dim3(8 * a.wg_per_xcd), dim3(kBatchThreads), bd.lds_bytes, st, a);
     return hipGetLastError();

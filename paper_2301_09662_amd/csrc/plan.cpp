@@ -106,11 +106,16 @@ struct epic_plan_s {
     std::vector<int> weights;        // cost of one spectrum per sub-array
     std::vector<BatchSub> table;     // host copy of bd.table
     int autotuned = 0;               // 1: timed at plan time, 2: taken from the tuning cache
+    // the partial-accumulator slots hold zeros (after plan creation and after a
+    // resetting read-out): the next accumulate call stores its sums instead of
+    // adding them, which saves reading the slots
+    int slots_zero = 1;
     // hipGraph replay of accumulate steps: one executable graph per (spectra
     // count, input pointers), the kGraphCache most recently used kept
     hipStream_t cap_stream = nullptr;
     struct GraphEntry {
         int64_t T;
+        int fresh;
         std::vector<const uint8_t*> ptrs;
         hipGraph_t graph;
         hipGraphExec_t exec;
@@ -619,11 +624,14 @@ hipError_t launch_one(const SubDev& d, const uint8_t* samples, int64_t n_time, h
 // The kernel launches of one accumulate step.
 hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
     if (p->batched) {
-        hipError_t e = launch_batch(p->bd, d_samples, (int)p->subs.size(), n_time, st);
+        BatchDev bd = p->bd;
+        bd.fresh = p->slots_zero;
+        hipError_t e = launch_batch(bd, d_samples, (int)p->subs.size(), n_time, st);
         if (e != hipSuccess) return e;
     } else {
         for (size_t k = 0; k < p->subs.size(); ++k) {
-            const SubDev& d = p->subs[k].dev;
+            SubDev d = p->subs[k].dev;
+            d.fresh = p->slots_zero;
             hipError_t e = launch_one(d, d_samples[k], n_time, st);
             if (e != hipSuccess) return e;
         }
@@ -640,16 +648,16 @@ hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t 
 }
 
 // Replay the step from a captured hipGraph.  Each (spectra count, input
-// pointers) gets its own executable graph; the kGraphCache most recently used
-// are kept, so a caller that rotates over a few input buffers replays instead
-// of capturing again.
+// pointers, first call after a reset or not) gets its own executable graph;
+// the kGraphCache most recently used are kept, so a caller that rotates over
+// a few input buffers replays instead of capturing again.
 constexpr size_t kGraphCache = 4;
 
 hipError_t launch_step_graph(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
     std::vector<const uint8_t*> ptrs(d_samples, d_samples + p->subs.size());
     epic_plan_s::GraphEntry* hit = nullptr;
     for (auto& g : p->graphs)
-        if (g.T == n_time && g.ptrs == ptrs) hit = &g;
+        if (g.T == n_time && g.fresh == p->slots_zero && g.ptrs == ptrs) hit = &g;
     if (!hit) {
         if (p->graphs.size() >= kGraphCache) {
             auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
@@ -658,7 +666,7 @@ hipError_t launch_step_graph(epic_plan_s* p, const uint8_t* const* d_samples, in
             (void)hipGraphDestroy(lru->graph);
             p->graphs.erase(lru);
         }
-        epic_plan_s::GraphEntry g{n_time, ptrs, nullptr, nullptr, 0};
+        epic_plan_s::GraphEntry g{n_time, p->slots_zero, ptrs, nullptr, nullptr, 0};
         hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
         hipError_t le = launch_step(p, d_samples, n_time, p->cap_stream);
@@ -1233,6 +1241,7 @@ epic_status epic_grid_fft_accumulate(epic_plan_t p, const uint8_t* const* d_samp
     if (e == hipSuccess)
         e = (p->desc.flags & EPIC_F_GRAPH) ? launch_step_graph(p, d_samples, n_time, st)
                                            : launch_step(p, d_samples, n_time, st);
+    if (e == hipSuccess) p->slots_zero = 0;
     return check_device(p, e);
 }
 
@@ -1262,6 +1271,7 @@ epic_status epic_readout(epic_plan_t p, float* const* d_images, int32_t reset, v
         if (e != hipSuccess) return check_device(p, e);
         if (!p->ac_pending.empty()) p->ac_pending[k] = 0;   // the read-out folded them
     }
+    if (reset) p->slots_zero = 1;
     return EPIC_OK;
 }
 
@@ -1293,7 +1303,10 @@ epic_status epic_image_noalloc(epic_plan_t p, const uint8_t* const* d_samples, i
     float* base = nullptr;
     hipError_t e = scratch_address(p->device, &base);
     if (e != hipSuccess) return check_device(p, e);
-    for (size_t k = 0; k < run.size(); ++k) run[k].slots = base + off[k];
+    for (size_t k = 0; k < run.size(); ++k) {
+        run[k].slots = base + off[k];
+        run[k].fresh = 1;   // cleared just below
+    }
     // clear with a fill kernel (no memset node if the caller captures this)
     e = launch_zero(base, (int64_t)need, st);
     for (size_t k = 0; k < run.size() && e == hipSuccess && n_time > 0; ++k) {
