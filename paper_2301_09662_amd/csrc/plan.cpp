@@ -651,7 +651,7 @@ hipError_t launch_step(epic_plan_s* p, const uint8_t* const* d_samples, int64_t 
 // pointers, first call after a reset or not) gets its own executable graph;
 // the kGraphCache most recently used are kept, so a caller that rotates over
 // a few input buffers replays instead of capturing again.
-constexpr size_t kGraphCache = 4;
+constexpr size_t kGraphCache = 8;
 
 hipError_t launch_step_graph(epic_plan_s* p, const uint8_t* const* d_samples, int64_t n_time, hipStream_t st) {
     std::vector<const uint8_t*> ptrs(d_samples, d_samples + p->subs.size());

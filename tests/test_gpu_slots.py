@@ -85,3 +85,30 @@ def test_first_call_stores_later_calls_add(E, which, precision, gridder, mode):
             assert E.epic_plan_query(plan)["graph_builds"] == 4
     finally:
         E.epic_destroy(plan)
+
+
+@pytest.mark.gpu
+def test_three_buffers_two_call_integrations_replay(E):
+    """A caller rotating over three input buffers with integrations of two
+    calls: six (buffer, first-call-or-not) graphs, captured in the first
+    round and replayed in the second, every integration equal to the oracle."""
+    torch, dev = torch_dev()
+    sub = synth.shrink(synth.workload(2).subs[0], n_chan=2)
+    n = 4
+    x = synth.samples(sub, 3 * n)
+    d = torch.from_numpy(x).to(dev)
+    bufs = [d[k * n:(k + 1) * n] for k in range(3)]
+    plan = E.epic_plan([sub], precision="fp32", max_time=n, flags=E.EPIC_F_GRAPH)
+    try:
+        for rnd in range(2):
+            for a, b in ((0, 1), (2, 0), (1, 2)):
+                E.epic_grid_fft_accumulate(plan, [bufs[a]], n)
+                E.epic_grid_fft_accumulate(plan, [bufs[b]], n)
+                o = torch.full((2, 4, 64, 64), float("nan"), device=dev)
+                E.epic_readout(plan, [o], 1)
+                torch.cuda.synchronize()
+                ref = oracle.image(sub, np.concatenate([x[a * n:(a + 1) * n], x[b * n:(b + 1) * n]]))
+                assert_parity(o.double().cpu().numpy(), ref, 1e-5, f"round {rnd} buffers {a}, {b}")
+            assert E.epic_plan_query(plan)["graph_builds"] == 6
+    finally:
+        E.epic_destroy(plan)
