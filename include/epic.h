@@ -84,7 +84,8 @@ typedef enum {
 
 enum {
     EPIC_F_GRAPH = 1u,            /* replay accumulate steps from captured hipGraphs, one per
-                                     (n_time, input pointers); the 4 most recent are kept */
+                                     (n_time, input pointers, first call after a reset or
+                                     not); the 8 most recent are kept */
     EPIC_F_AUTOTUNE = 2u,         /* time candidate launch shapes at plan time: per FP16 sub-array
                                      with EPIC_GRID_AUTO the gather form (gather program in LDS
                                      or streamed from L2) against the block-GEMM form at every
