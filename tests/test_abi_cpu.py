@@ -252,3 +252,20 @@ def test_autocorr_fold_limit_setting(E, monkeypatch):
             assert info["autocorr_pending"] == [0]
         finally:
             E.epic_destroy(p)
+
+
+def test_binding_refuses_to_load_without_the_library(tmp_path):
+    """The product path has no CPU fallback: a copy of the package without
+    libepic.so fails on import, naming the missing library."""
+    import shutil
+    import subprocess
+    import sys as _sys
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2301_09662_amd")
+    dst = tmp_path / "paper_2301_09662_amd"
+    dst.mkdir()
+    for f in ("__init__.py", "epic.py"):
+        shutil.copy(os.path.join(pkg, f), dst / f)
+    r = subprocess.run([_sys.executable, "-c", "import paper_2301_09662_amd.epic"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "libepic.so is missing" in r.stderr and "no CPU fallback" in r.stderr
