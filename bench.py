@@ -8,8 +8,8 @@ resident in HBM before the timed region.  Prints ONE JSON line.
 
 Besides the workload's own form, the reduced-precision legs time the same
 shape with the transforms on the FP16 matrix cores and gridding either as the
-FP32 gather or as a block-sparse product on the matrix cores (FP16 or FP8
-operands).  The FP64 oracle, timed on the host's cores, also gives every form's
+FP32 gather or as a product on the matrix cores (block-sparse FP16 and FP8
+operands, and the dense kernel matrix in FP16).  The FP64 oracle, timed on the host's cores, also gives every form's
 per-channel image error over the same spectra.
 
 Workload (default): the station-scale FP32 configuration -- 256 dual-pol
@@ -59,16 +59,18 @@ KERNEL_SOURCES = {
     "fp16": ["kernels_mfma.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_gather.hpp", "epic_sched.hpp",
              "epic_internal.hpp"],
     "bgemm": ["kernels_bgemm.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_sched.hpp", "epic_internal.hpp"],
+    "dense": ["kernels_bgemm.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_sched.hpp", "epic_internal.hpp"],
     "direct": ["kernels_direct.hip", "epic_mfma.hpp", "epic_device.hpp", "epic_gather.hpp", "epic_internal.hpp"],
 }
 
 
 def kernel_family(precision, info, k=0):
     """Hot kernel of a plan's sub-array k: the FP32 kernel, the matrix-core
-    gather kernel, the GEMM-gridding kernel (FP16 / FP8) or the direct form."""
+    gather kernel, the GEMM-gridding kernel (FP16 / FP8; dense or block-sparse
+    tables, counted apart) or the direct form."""
     if precision == "fp32":
         return "fp32"
-    return {1: "fp16", 2: "bgemm", 3: "bgemm", 4: "direct"}[info["grid_form"][k]]
+    return {1: "fp16", 2: "dense", 3: "bgemm", 4: "direct"}[info["grid_form"][k]]
 
 
 def sources_sha256(family):
@@ -260,7 +262,7 @@ def main():
     ap.add_argument("--cfg", type=int, default=2, help="workload config (default: station FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-precision legs")
-    ap.add_argument("--legs", default="fp16:gather,fp16:block,fp8:block",
+    ap.add_argument("--legs", default="fp16:gather,fp16:block,fp16:dense,fp8:block",
                     help="reduced-precision legs of an FP32 workload, precision:gridder, comma-separated")
     ap.add_argument("--gridder", choices=["auto", "gather", "dense", "block", "direct"], default="auto",
                     help="gridding form of the workload's own run")
