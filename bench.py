@@ -254,6 +254,62 @@ def cpu_numpy_fft(sub, samples, budget_s=10.0):
                       f"FP32 sparse gridding + FFT)"}
 
 
+def run_sweep(kind, steps, warmup):
+    """The paper's measurement axes (Sec. 3.1 and 3.2, Figs. 3 and 4): time per
+    accumulate call of the station shape against the channel count at 64 x 64
+    (1000 spectra), and against the grid size at 4 channels, for the FP32 form
+    and the FP16 matrix-core form.  The work does not depend on the sample
+    values, so the inputs are uniform random bytes drawn on the device."""
+    import dataclasses
+
+    import torch
+    from paper_2301_09662_amd import epic as E
+
+    base = synth.workload(2).subs[0]
+    T = 1000
+    if kind == "channels":
+        shapes = [(dataclasses.replace(base, n_chan=c), {"n_chan": c, "grid_n": base.grid_n})
+                  for c in (1, 2, 4, 8, 16, 33, 66, 132)]
+    else:
+        shapes = [(dataclasses.replace(base, n_chan=4, grid_n=n), {"n_chan": 4, "grid_n": n})
+                  for n in (32, 48, 64, 96, 128, 192, 256)]
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(230109662)
+    points = []
+    for sub, key in shapes:
+        x = torch.randint(0, 256, (T, sub.n_chan, sub.n_ant, sub.n_pol), dtype=torch.uint8, device=dev,
+                          generator=gen)
+        pt = dict(key)
+        for prec in ("fp32", "fp16"):
+            plan = E.epic_plan([sub], precision=prec, max_time=T, gridder="gather")
+            try:
+                info = E.epic_plan_query(plan)
+                out = torch.empty((sub.n_chan, info["npp"][0], sub.grid_n, sub.grid_n), device=dev)
+                ms = []
+                for k in range(warmup + steps):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    E.epic_grid_fft_accumulate(plan, [x], T, stream)
+                    b.record(stream)
+                    E.epic_readout(plan, [out], 1, stream)
+                    torch.cuda.synchronize()
+                    if k >= warmup:
+                        ms.append(a.elapsed_time(b))
+            finally:
+                E.epic_destroy(plan)
+            med = float(np.median(ms))
+            pt[f"{prec}_ms"] = med
+            pt[f"{prec}_samples_per_s"] = sub.n_ant * sub.n_pol * sub.n_chan * T / (med * 1e-3)
+            pt[f"{prec}_tflops"] = algorithmic_flops_per_ct(sub) * sub.n_chan * T / (med * 1e-3) / 1e12
+        pt["fp16_speedup"] = pt["fp32_ms"] / pt["fp16_ms"]
+        points.append(pt)
+    print(json.dumps({"sweep": kind, "workload": "station layout (256 ant x 2 pol, dl = 1), 1000 spectra per "
+                      "call, accumulate kernel time (HIP events, median)", "steps": steps, "warmup": warmup,
+                      "points": points}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +325,9 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp16", "fp8"], default=None,
                     help="override the workload's own precision")
     ap.add_argument("--no-graph", action="store_true", help="batched workloads: eager launches instead of graph replay")
+    ap.add_argument("--sweep", choices=["channels", "grid"], default=None,
+                    help="only time the station shape against the channel count (64 x 64) or the grid size "
+                         "(4 channels), FP32 and FP16, and print one JSON line of points")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE hardware counters")
@@ -287,6 +346,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(channels shard across GPUs with no exchange; not built here)"}))
         sys.exit(2)
+    if args.sweep:
+        run_sweep(args.sweep, args.steps, args.warmup)
+        return
 
     import torch
     from paper_2301_09662_amd import epic as E
